@@ -1,0 +1,224 @@
+/*
+ * vmcdet — determinant ratios of consecutive sparse Slater matrices for
+ * Variational Monte Carlo on insulators, on AMD MI355X (gfx950).
+ *
+ * Method: Ahuja, Clark, de Sturler, Ceperley, Kim, "Improved Scaling for
+ * Quantum Monte Carlo on Insulators" (arXiv 1008.5113).  Each Metropolis step
+ * moves one particle i; the Slater matrix changes by one row,
+ * A' = A + e_i u^T (eqs. (MatrixUpdate_1), (matrixUpdate2)), and the move is
+ * accepted with probability |det A'/det A|^2 = |1 + u^T A^{-1} e_i|^2
+ * (eq. (detRatioEq)).  The library obtains z = A^{-1} e_i with
+ * right-preconditioned full GMRES (Section 3.2, eq. (precondSystem)), an ILUTP
+ * preconditioner A Q ~ L U (eq. (ilu)) that is kept across steps by the
+ * rank-one updates M_{k+1} = (I - zhat u^T) M_k (eqs. (finalMk0), (mkp1),
+ * (finalMkm)), the geometric particle/orbital reordering (Section 3.1) and
+ * the effective-stability monitor N (eq. (stabilityVecEq)) with the reorder
+ * triggers of Section 4.
+ *
+ * Conventions
+ * - Every entry point returns a vmc_status: 0 on success, a negative code on
+ *   failure (see VMC_E*); vmc_last_error() returns a message for the context.
+ *   No C++ exception crosses this interface.
+ * - A context owns all device memory it allocates; host arrays passed in are
+ *   copied and stay owned by the caller.
+ * - Work is issued on the HIP stream given to vmc_create (NULL = default
+ *   stream).  Calls that write host outputs synchronise that stream before
+ *   returning; vmc_run_steps with a device log pointer is asynchronous.
+ * - A context is not thread-safe; one context per stream.
+ * - Walker w's state: particle positions, the Slater matrix stored by row
+ *   positions (a permutation of particles) and column positions (a
+ *   permutation of orbitals), the current ILUTP factors and the list of
+ *   rank-one updates.  Ratios are independent of the permutations because a
+ *   simultaneous row and column permutation cancels in det A'/det A.
+ */
+#ifndef VMCDET_H
+#define VMCDET_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t vmc_status;
+
+#define VMC_OK 0
+#define VMC_EINVAL (-1)     /* invalid argument (sizes, NULL pointers, ranges) */
+#define VMC_ENOMEM (-2)     /* device or host allocation failed */
+#define VMC_EHIP (-3)       /* HIP runtime error; message in vmc_last_error */
+#define VMC_ENOCONV (-4)    /* GMRES did not converge even after reorder + refactor */
+#define VMC_ESINGULAR (-5)  /* zero pivot in ILUTP that reordering did not remove */
+#define VMC_ECAPACITY (-6)  /* a Slater row or an ILUTP work row exceeded its capacity */
+#define VMC_ESTATE (-7)     /* call out of order (e.g. accept without a pending ratio) */
+
+#define VMC_PREC_FP64 0     /* FP64 everywhere */
+#define VMC_PREC_MIXED 1    /* FP32 SpMV/factors/Krylov, FP64 residual, ratio, monitor */
+
+#define VMC_ORB_GAUSS 0     /* phi_j(r) = exp(-|d|^2 / (2 sigma_j^2)) */
+#define VMC_ORB_GAUSS_PX 1  /* + p_scale * d_x * exp(-|d|^2 / (2 p_sigma^2)) */
+
+/* Step-record flag bits */
+#define VMC_FLAG_ACCEPTED 1
+#define VMC_FLAG_REORDERED 2     /* a trigger fired: reorder + refactor + re-solve */
+#define VMC_FLAG_REFACTORED 4    /* periodic refactor after m_max stored updates */
+#define VMC_FLAG_CONVERGED 8     /* the final solve met its tolerance */
+#define VMC_FLAG_SINGULAR 16
+#define VMC_FLAG_CAPACITY 32
+
+/* Solver and chain parameters.  Zero-initialise and call vmc_default_params. */
+typedef struct vmc_params {
+  int32_t precision;        /* VMC_PREC_FP64 or VMC_PREC_MIXED */
+  int32_t gmres_maxit;      /* full GMRES, no restart (Section 4: 40); <= 64 */
+  double gmres_rtol;        /* FP64 path: stop when ||r|| <= rtol * ||b|| */
+  double droptol;           /* ILUTP relative drop tolerance (times ||a_i||_2) */
+  double permtol;           /* ILUTP: swap columns when permtol*|max| > |diag| */
+  int32_t lfil;             /* extra fill per L row and per U row; < 0: ceil(nnz/(2n)) */
+  int32_t m_max;            /* stored rank-one updates before a refactor (>= 1) */
+  double n_thresh;          /* reorder when the effective stability N exceeds this */
+  double iter_factor;       /* reorder when iterations >= factor * running average */
+  int32_t iter_min_solves;  /* solves before the iteration average is used */
+  double inner_rtol;        /* mixed: inner FP32 solve tolerance */
+  double refine_tol;        /* mixed: stop when ||e_i - A z|| <= tol * min(1, |ratio|) */
+  int32_t refine_maxit;     /* mixed: maximum refinement passes */
+  double step;              /* proposal half-width h (uniform cube) */
+  int32_t row_cap;          /* nonzeros per stored Slater row; <= 0: automatic */
+  int32_t force_reorder_every; /* test knob: trigger every k-th step (0 = off) */
+  int32_t block_threads;    /* threads per walker workgroup (256 or 512; 0 = auto) */
+  int32_t reserved[7];
+} vmc_params;
+
+/* One walker: its physical system (orbital centres and shapes) and start. */
+typedef struct vmc_walker_init {
+  int32_t n;                /* particles = orbitals, 1 <= n <= 16384 */
+  int32_t lattice[3];       /* site counts per axis; box = lattice * a */
+  double a;                 /* lattice spacing */
+  double site_margin;       /* max per-axis distance of a site from its lattice point */
+  const double* sites;      /* host, n*3, orbital centres in [0, box) (site j nominally at
+                               (j % Lx, (j / Lx) % Ly, j / (Lx*Ly)) * a) */
+  const double* sigma;      /* host, n, Gaussian width of each orbital */
+  int32_t orbital_kind;     /* VMC_ORB_* */
+  double p_scale;
+  double p_sigma;
+  double cutoff;            /* orbital j vanishes where the minimum-image distance > cutoff */
+  const double* pos0;       /* host, n*3, initial positions in [0, box) */
+  uint64_t seed;            /* Philox key word 0 for this walker's draws */
+} vmc_walker_init;
+
+/* Per-step outcome, also used as the record of the step log. */
+typedef struct vmc_step_record {
+  int64_t step;             /* the walker's step index g (Philox counter) */
+  int32_t walker;
+  int32_t particle;         /* particle id moved */
+  double new_pos[3];
+  double ratio;             /* det A'/det A, FP64 */
+  double u_acc;             /* acceptance draw in (0,1) */
+  double N;                 /* effective stability of the (last) solve */
+  double resid;             /* final residual norm ||e_i - A z||_2 (estimate in FP64 path) */
+  int32_t iters;            /* GMRES iterations of the final solve (all inner solves, mixed) */
+  int32_t flags;            /* VMC_FLAG_* */
+} vmc_step_record;
+
+/* Host copies of a walker's state (any pointer may be NULL to skip). */
+typedef struct vmc_state_view {
+  double* pos;              /* n*3, by particle id */
+  int32_t* row_particle;    /* n: particle at each row position */
+  int32_t* col_site;        /* n: orbital (site id) at each column position */
+  int32_t* reorder_row;     /* n: last geometric reorder, particle per position */
+  int32_t* reorder_col;     /* n: last geometric reorder, site per position */
+  int32_t* a_len;           /* n: nonzeros per Slater row (by row position) */
+  int32_t* a_col;           /* n*row_cap: column positions */
+  double* a_val;            /* n*row_cap */
+  int32_t* l_len;           /* n */
+  int32_t* l_col;           /* n*fact_cap: column positions (< row) */
+  double* l_val;            /* n*fact_cap: multipliers l_ik */
+  int32_t* u_len;           /* n: off-diagonal count */
+  int32_t* u_col;           /* n*fact_cap: column positions (> row) */
+  double* u_val;            /* n*fact_cap: u_ik */
+  double* u_diag;           /* n */
+  int32_t* ilu_perm;        /* n: column permutation q of the last ILUTP, relative to the
+                               column numbering A had when it was factored */
+  int64_t* step;            /* 1: steps taken */
+  int32_t* n_updates;       /* 1: stored rank-one updates */
+} vmc_state_view;
+
+/* Per-walker counters. */
+typedef struct vmc_stats {
+  int64_t steps, accepted, solves, iters, reorders, refactors, nonconverged;
+  int64_t inner_solves, refine_passes;
+  double max_N, sum_N;
+  int32_t status;           /* VMC_OK or the first error the walker hit */
+  int32_t pad;
+} vmc_stats;
+
+/* Fill p with the defaults (Section 4 settings where the paper gives them). */
+vmc_status vmc_default_params(vmc_params* p);
+
+/* Create a context for n_walkers walkers; copies all host arrays.  hip_stream
+   is a hipStream_t (NULL for the default stream). */
+vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers,
+                      const vmc_walker_init* walkers, void* hip_stream);
+
+/* Evaluate every Slater row from the current positions (Section 2.1,
+   eq. (SlaterMatrix)): a_{ij} = phi_j(r_i) for minimum-image distances within
+   the cutoff.  walkers = NULL means all. */
+vmc_status vmc_build_slater(void* ctx, const int32_t* walkers, int32_t count);
+
+/* Compute a new preconditioner: with reorder != 0, first the geometric
+   particle/orbital reordering (Section 3.1) and a rebuild of the Slater matrix
+   in that order; then ILUTP (Section 3.2, eq. (ilu); Section 4 settings) and
+   clearing of the rank-one update list.  walkers = NULL means all. */
+vmc_status vmc_ilutp(void* ctx, const int32_t* walkers, int32_t count, int32_t reorder);
+
+/* Determinant ratio of a trial move for each listed walker (eq. (detRatioEq)):
+   ratio = 1 + u^T z with A z = e_i by preconditioned GMRES, with the reorder
+   triggers of Section 4.  particle / new_pos (host, count and count*3) give
+   the move; NULL draws it from the walker's Philox stream (particle = step mod
+   n).  ratio_out (host, count) and info_out (host, count, may be NULL) receive
+   the results; the move stays pending until vmc_accept. */
+vmc_status vmc_det_ratio(void* ctx, const int32_t* walkers, int32_t count,
+                         const int32_t* particle, const double* new_pos,
+                         double* ratio_out, vmc_step_record* info_out);
+
+/* Commit or discard each pending move.  accept (host, count) forces the
+   decision; NULL applies the Metropolis rule ratio^2 > u_acc with the
+   walker's draw (Section 2.2).  On acceptance the row is replaced and the
+   preconditioner updated (eq. (mkp1)); after m_max updates it is refactored.
+   accepted_out (host, count, may be NULL) receives the decisions. */
+vmc_status vmc_accept(void* ctx, const int32_t* walkers, int32_t count,
+                      const uint8_t* accept, uint8_t* accepted_out);
+
+/* Persistent fused path: every walker takes `steps` Metropolis steps (propose,
+   row, ratio, decision, update, refactor/reorder as triggered) in one launch,
+   each walker on its own workgroup.  dev_log (device memory, may be NULL)
+   receives record [w * steps + s] if log_cap allows.  Asynchronous. */
+vmc_status vmc_run_steps(void* ctx, int32_t steps, vmc_step_record* dev_log, int64_t log_cap);
+
+/* vmc_run_steps with steps = sweeps * n of each walker (a sweep moves every
+   particle once); requires all walkers to share n.  Asynchronous. */
+vmc_status vmc_run_sweeps(void* ctx, int32_t sweeps, vmc_step_record* dev_log, int64_t log_cap);
+
+/* Wait for all work issued on the context's stream; returns the first walker
+   error (if any) as a status. */
+vmc_status vmc_sync(void* ctx);
+
+/* Sizes of walker w: n, stored Slater row capacity, factor row capacity. */
+vmc_status vmc_get_dims(void* ctx, int32_t walker, int32_t* n, int32_t* row_cap,
+                        int32_t* fact_cap);
+
+/* Copy walker w's state to host buffers (synchronises). */
+vmc_status vmc_get_state(void* ctx, int32_t walker, const vmc_state_view* view);
+
+/* Copy per-walker counters to stats_out[n_walkers] (synchronises). */
+vmc_status vmc_get_stats(void* ctx, vmc_stats* stats_out);
+
+/* Last error message of the context (or of the last failed vmc_create when ctx is NULL). */
+const char* vmc_last_error(void* ctx);
+
+/* Free the context and all its device memory. */
+vmc_status vmc_destroy(void* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VMCDET_H */

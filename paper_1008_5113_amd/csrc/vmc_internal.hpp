@@ -1,0 +1,128 @@
+// Internal types of the vmcdet library (host and device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vmcdet.h"
+
+namespace vmc {
+
+constexpr int NT = 512;        // threads per walker workgroup
+constexpr int NWAVE = NT / 64;
+constexpr int BLK = 64;        // rows per triangular-solve block (one lane per row)
+constexpr int MAXIT = 64;      // largest supported GMRES iteration count
+constexpr int NZMAX = 2048;    // ILUTP work-row entry capacity
+constexpr int LMAX = 1024;     // ILUTP multipliers per row before the fill limit
+constexpr int MMAX_CAP = 256;  // largest supported m_max
+
+// Walker-level error codes stored on the device (mapped to vmc_status on the host).
+constexpr int WST_OK = 0;
+constexpr int WST_CAPACITY = 1;
+constexpr int WST_SINGULAR = 2;
+constexpr int WST_NOCONV = 4;
+
+struct DevParams {
+  int precision;
+  int maxit;
+  double rtol;
+  double droptol, permtol;
+  int lfil;
+  int m_max;
+  double n_thresh, iter_factor;
+  int iter_min_solves;
+  double inner_rtol, refine_tol;
+  int refine_maxit;
+  double step;
+  int force_reorder_every;
+};
+
+// Everything the device needs about one walker.  Arrays are per walker; the
+// Slater matrix is stored by row position with capacity W per row, the ILU
+// factors with capacity F per row.  Column indices of A, L, U, the update
+// vectors and all Krylov vectors live in the same column numbering (the
+// current "column positions"), so the preconditioner's column permutation is
+// folded into that numbering at every factorisation.
+struct Walker {
+  // sizes
+  int n, W, F, UC;            // n, Slater row cap, factor row cap, update-vector cap
+  int lat[3];
+  int kind;
+  double box[3], a, margin, cutoff, p_scale, p_sigma;
+  unsigned long long seed;
+
+  // system (by site id) and positions (by particle id)
+  const double* sites;        // n*3
+  const double* sigma;        // n
+  double* pos;                // n*3
+
+  // orderings
+  int* rowperm;               // row position -> particle
+  int* rpos;                  // particle -> row position
+  int* cpos;                  // site -> column position
+  int* colsite;               // column position -> site
+  int* reo_row;               // last geometric reorder (particle per position)
+  int* reo_col;               // last geometric reorder (site per position)
+
+  // Slater matrix
+  int* a_len;
+  int* a_col;
+  double* a_val;
+  float* a_val32;
+
+  // ILU factors (column positions); U stored off-diagonal, scaled copies for the solve
+  int* l_len;
+  int* l_col;
+  double* l_val;
+  float* l_val32;
+  int* u_len;
+  int* u_col;
+  double* u_val;              // unscaled off-diagonal U
+  double* u_diag;
+  double* us_val;             // D^{-1} U off-diagonal (FP64 solve)
+  float* us_val32;            // D^{-1} U off-diagonal (FP32 solve)
+  double* u_dinv;
+  float* u_dinv32;
+  int* ilu_q;                 // last ILUTP column permutation (labels before it)
+
+  // rank-one updates M <- (I - zhat u^T) M, oldest first
+  double* Z64;                // m_max * n
+  float* Z32;
+  int* up_len;                // m_max
+  int* up_col;                // m_max * UC
+  double* up_val;
+  float* up_val32;
+  double* T;                  // m_max * m_max: T[s*m_max+t] = u_s^T zhat_t (t < s)
+
+  // Krylov workspace (typed by the solve precision)
+  void* V;                    // (maxit+1) * n
+  void* Xp;                   // maxit * n : preconditioned basis vectors
+  void* wv;                   // n
+  double* zvec;               // n : solution z (FP64 accumulation)
+  double* rvec;               // n : FP64 residual (mixed)
+
+  // pending move
+  int* new_col;               // W
+  double* new_val;            // W
+  int* pu_col;                // UC
+  double* pu_val;             // UC
+};
+
+// Mutable per-walker scalars, kept apart from the (read-mostly) pointer table.
+struct WalkerState {
+  long long g;                // steps taken (Philox counter)
+  int m;                      // stored updates
+  int status;                 // WST_* bits
+  int pend_valid, pend_p, pend_i, pend_newlen, pend_ulen, pend_flags, pend_iters;
+  int pad0;
+  double pend_newpos[3];
+  double pend_ratio, pend_uacc, pend_N, pend_resid;
+  double avg_iters;           // running mean of first-solve iteration counts
+  long long avg_count;
+  // counters
+  long long st_steps, st_acc, st_solves, st_iters, st_reorders, st_refactors, st_nonconv;
+  long long st_inner, st_refine;
+  double st_maxN, st_sumN;
+};
+
+}  // namespace vmc

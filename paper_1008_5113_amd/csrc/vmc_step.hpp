@@ -1,0 +1,328 @@
+// One Metropolis step of one walker (workgroup-level): proposal, new row and
+// u, determinant ratio, reorder triggers, decision, row replacement and
+// preconditioner update.
+#pragma once
+
+#include "vmc_krylov.hpp"
+#include "vmc_setup.hpp"
+
+namespace vmc {
+
+// New row of particle p at rnew (column positions) and u = new row - old row
+// (eq. (matrixUpdateU)), written to the walker's pending buffers.  Returns
+// WST_*; the row position and the lengths come back through S.ic[4..6].
+__device__ inline int wg_prepare(const Walker& W, Smem& S, int p, const double* rnew) {
+  const int i = W.rpos[p];
+  if (wave_id() == 0) {
+    const int lane = lane_id();
+    int st = WST_OK;
+    const int cnt = wave_row(W, rnew[0], rnew[1], rnew[2], W.cpos, W.new_col, W.new_val, nullptr, W.W);
+    int ul = 0;
+    if (cnt > W.W) {
+      st = WST_CAPACITY;
+    } else {
+      __threadfence_block();
+      const int lo = W.a_len[i];
+      const int* oc = W.a_col + (size_t)i * W.W;
+      const double* ov = W.a_val + (size_t)i * W.W;
+      for (int e = lane; e < cnt; e += 64) {
+        const int c = W.new_col[e];
+        double vo = 0.0;
+        for (int f = 0; f < lo; ++f)
+          if (oc[f] == c) { vo = ov[f]; break; }
+        W.pu_col[e] = c;
+        W.pu_val[e] = W.new_val[e] - vo;
+      }
+      ul = cnt;
+      for (int e0 = 0; e0 < lo; e0 += 64) {
+        const int e = e0 + lane;
+        bool miss = false;
+        int c = 0;
+        if (e < lo) {
+          c = oc[e];
+          miss = true;
+          for (int f = 0; f < cnt; ++f)
+            if (W.new_col[f] == c) { miss = false; break; }
+        }
+        unsigned long long mask = __ballot(miss);
+        const int before = __popcll(mask & ((1ull << lane) - 1ull));
+        if (miss) {
+          W.pu_col[ul + before] = c;
+          W.pu_val[ul + before] = -ov[e];
+        }
+        ul += __popcll(mask);
+      }
+      __threadfence_block();
+    }
+    if (lane == 0) {
+      S.ic[4] = i;
+      S.ic[5] = cnt;
+      S.ic[6] = ul;
+      S.ic[7] = st;
+    }
+  }
+  __syncthreads();
+  const int st = S.ic[7];
+  return st;
+}
+
+struct StepSolve {
+  double ratio;
+  int iters_first;  // iterations of the first (inner) solve
+  int iters_total;
+  int conv_first;
+  int conv;
+  double N;
+  double res;
+  int inner;
+  int passes;
+};
+
+// ratio = 1 + u^T z with A z = e_i (eq. (detRatioEq)).
+template <int PREC>
+__device__ inline StepSolve wg_solve(const Walker& W, int m, const DevParams& P, Smem& S, int i, int ulen) {
+  StepSolve o;
+  if (PREC == VMC_PREC_FP64) {
+    SolveOut g = wg_gmres<double>(W, m, P, S, i, nullptr, 1.0, P.rtol, P.maxit, W.zvec, 1.0, true);
+    o.ratio = wg_ratio(W, ulen, W.zvec, S);
+    o.iters_first = o.iters_total = g.iters;
+    o.conv_first = o.conv = g.conv;
+    o.N = g.N;
+    o.res = g.res;
+    o.inner = 1;
+    o.passes = 0;
+  } else {
+    // FP32 inner solves, FP64 residual, ratio and monitor (iterative refinement)
+    SolveOut g = wg_gmres<float>(W, m, P, S, i, nullptr, 1.0, P.inner_rtol, P.maxit, W.zvec, 1.0, true);
+    o.iters_first = g.iters;
+    o.iters_total = g.iters;
+    o.conv_first = g.conv;
+    o.N = g.N;
+    o.inner = 1;
+    o.conv = 0;
+    int pass = 0;
+    while (true) {
+      const double rn = wg_resid64(W, W.zvec, i, W.rvec, S);
+      o.ratio = wg_ratio(W, ulen, W.zvec, S);
+      o.res = rn;
+      if (rn <= P.refine_tol * fmin(1.0, fabs(o.ratio))) { o.conv = 1; break; }
+      if (pass >= P.refine_maxit || !(rn > 0.0)) break;
+      ++pass;
+      SolveOut c = wg_gmres<float>(W, m, P, S, -1, W.rvec, rn, P.inner_rtol, P.maxit, W.zvec, rn, false);
+      o.N = fmax(o.N, c.N);
+      o.iters_total += c.iters;
+      ++o.inner;
+    }
+    o.passes = pass;
+  }
+  return o;
+}
+
+// Geometric reorder, rebuild of A in the new order, ILUTP (Section 3.1/3.2).
+template <int PREC>
+__device__ inline int wg_reorder_refactor(const Walker& W, const DevParams& P, Smem& S) {
+  wg_reorder(W, S);
+  int st = wg_build_all_rows(W, S);
+  if (st != WST_OK) return st;
+  return wg_ilutp(W, P, S);
+}
+
+// Append the rank-one factor of an accepted move (eq. (mkp1)): zhat = z/ratio,
+// u; G = (I + T)^{-1} gains a row.
+template <int PREC>
+__device__ inline void wg_append_update(const Walker& W, const DevParams& P, Smem& S, int s, double ratio,
+                                        int ulen) {
+  const int n = W.n, mm = P.m_max;
+  const double inv = 1.0 / ratio;
+  for (int r = threadIdx.x; r < n; r += NT) {
+    const double zh = W.zvec[r] * inv;
+    if (PREC == VMC_PREC_FP64) W.Z64[(size_t)s * n + r] = zh;
+    else W.Z32[(size_t)s * n + r] = (float)zh;
+  }
+  for (int e = threadIdx.x; e < ulen; e += NT) {
+    W.up_col[(size_t)s * W.UC + e] = W.pu_col[e];
+    W.up_val[(size_t)s * W.UC + e] = W.pu_val[e];
+    W.up_val32[(size_t)s * W.UC + e] = (float)W.pu_val[e];
+  }
+  if (threadIdx.x == 0) W.up_len[s] = ulen;
+  __threadfence_block();
+  __syncthreads();
+  // t_l = u_s^T zhat_l, l < s, in the precision the apply uses
+  for (int l = wave_id(); l < s; l += NWAVE) {
+    double acc = 0.0;
+    for (int e = lane_id(); e < ulen; e += 64) {
+      const int c = W.up_col[(size_t)s * W.UC + e];
+      if (PREC == VMC_PREC_FP64) acc += W.up_val[(size_t)s * W.UC + e] * W.Z64[(size_t)l * n + c];
+      else acc += (double)(W.up_val32[(size_t)s * W.UC + e] * W.Z32[(size_t)l * n + c]);
+    }
+    acc = wave_sum(acc);
+    if (lane_id() == 0) S.gb[l] = acc;
+  }
+  __syncthreads();
+  // G[s][t] = -sum_{l=t}^{s-1} t_l G[l][t];  G[s][s] = 1
+  for (int t = threadIdx.x; t <= s; t += NT) {
+    double v = 1.0;
+    if (t < s) {
+      double acc = 0.0;
+      for (int l = t; l < s; ++l) acc += S.gb[l] * W.T[(size_t)l * mm + t];
+      v = -acc;
+    }
+    W.T[(size_t)s * mm + t] = v;
+  }
+  __threadfence_block();
+  __syncthreads();
+}
+
+// Ratio of a trial move (particle p to rnew), with the reorder triggers of
+// Section 4: N > n_thresh, first solve not converged, or iterations >=
+// iter_factor * running average.  Leaves the pending state in the walker.
+template <int PREC>
+__device__ inline void wg_det_ratio(const Walker& W, WalkerState* ws, const DevParams& P, Smem& S, int p,
+                                    const double* rnew, double u_acc) {
+  if (threadIdx.x == 0) S.ic[8] = 0;
+  __syncthreads();
+  int flags = 0;
+  int st = wg_prepare(W, S, p, rnew);
+  int i = S.ic[4];
+  int ulen = S.ic[6];
+  StepSolve o;
+  o.ratio = 0.0;
+  o.iters_first = o.iters_total = 0;
+  o.conv = o.conv_first = 0;
+  o.N = 0.0;
+  o.res = 0.0;
+  o.inner = o.passes = 0;
+  if (st == WST_OK) {
+    const int m = ws->m;
+    o = wg_solve<PREC>(W, m, P, S, i, ulen);
+    const long long g = ws->g;
+    const double avg = ws->avg_iters;
+    const long long navg = ws->avg_count;
+    bool trig = (o.N > P.n_thresh) || !o.conv_first ||
+                (navg >= P.iter_min_solves && (double)o.iters_first >= P.iter_factor * avg) ||
+                (P.force_reorder_every > 0 && ((g + 1) % P.force_reorder_every) == 0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      ws->avg_count = navg + 1;
+      ws->avg_iters = avg + ((double)o.iters_first - avg) / (double)(navg + 1);
+      ws->st_solves += 1;
+      ws->st_inner += o.inner;
+      ws->st_refine += o.passes;
+    }
+    if (trig) {
+      flags |= VMC_FLAG_REORDERED;
+      st = wg_reorder_refactor<PREC>(W, P, S);
+      if (threadIdx.x == 0) {
+        ws->m = 0;
+        ws->st_reorders += 1;
+        ws->st_refactors += 1;
+      }
+      __threadfence_block();
+      __syncthreads();
+      if (st == WST_OK) st = wg_prepare(W, S, p, rnew);
+      if (st == WST_OK) {
+        i = S.ic[4];
+        ulen = S.ic[6];
+        o = wg_solve<PREC>(W, 0, P, S, i, ulen);
+        if (threadIdx.x == 0) {
+          ws->st_solves += 1;
+          ws->st_inner += o.inner;
+          ws->st_refine += o.passes;
+        }
+      }
+    }
+  }
+  if (o.conv) flags |= VMC_FLAG_CONVERGED;
+  if (st & WST_SINGULAR) flags |= VMC_FLAG_SINGULAR;
+  if (st & WST_CAPACITY) flags |= VMC_FLAG_CAPACITY;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ws->pend_valid = (st == WST_OK) ? 1 : 0;
+    ws->pend_p = p;
+    ws->pend_i = i;
+    ws->pend_newlen = S.ic[5];
+    ws->pend_ulen = ulen;
+    ws->pend_flags = flags;
+    ws->pend_iters = o.iters_total;
+    ws->pend_newpos[0] = rnew[0];
+    ws->pend_newpos[1] = rnew[1];
+    ws->pend_newpos[2] = rnew[2];
+    ws->pend_ratio = o.ratio;
+    ws->pend_uacc = u_acc;
+    ws->pend_N = o.N;
+    ws->pend_resid = o.res;
+    ws->st_iters += o.iters_total;
+    ws->st_sumN += o.N;
+    if (o.N > ws->st_maxN) ws->st_maxN = o.N;
+    if (!o.conv) ws->st_nonconv += 1;
+    if (st != WST_OK) ws->status |= st;
+  }
+  __threadfence_block();
+  __syncthreads();
+}
+
+// Commit (accept != 0) or discard the pending move; advance the step counter.
+template <int PREC>
+__device__ inline void wg_accept(const Walker& W, WalkerState* ws, const DevParams& P, Smem& S, int accept,
+                                 int widx, vmc_step_record* rec) {
+  const int p = ws->pend_p, i = ws->pend_i;
+  const int newlen = ws->pend_newlen, ulen = ws->pend_ulen;
+  const double ratio = ws->pend_ratio;
+  int flags = ws->pend_flags;
+  int st = WST_OK;
+  if (accept) {
+    flags |= VMC_FLAG_ACCEPTED;
+    for (int e = threadIdx.x; e < newlen; e += NT) {
+      W.a_col[(size_t)i * W.W + e] = W.new_col[e];
+      const double v = W.new_val[e];
+      W.a_val[(size_t)i * W.W + e] = v;
+      W.a_val32[(size_t)i * W.W + e] = (float)v;
+    }
+    if (threadIdx.x == 0) {
+      W.a_len[i] = newlen;
+      W.pos[3 * p] = ws->pend_newpos[0];
+      W.pos[3 * p + 1] = ws->pend_newpos[1];
+      W.pos[3 * p + 2] = ws->pend_newpos[2];
+    }
+    __threadfence_block();
+    __syncthreads();
+    const int m = ws->m;
+    if (m + 1 >= P.m_max) {
+      st = wg_ilutp(W, P, S);
+      flags |= VMC_FLAG_REFACTORED;
+      if (threadIdx.x == 0) {
+        ws->m = 0;
+        ws->st_refactors += 1;
+      }
+    } else {
+      wg_append_update<PREC>(W, P, S, m, ratio, ulen);
+      if (threadIdx.x == 0) ws->m = m + 1;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (rec) {
+      rec->step = ws->g;
+      rec->walker = widx;
+      rec->particle = p;
+      rec->new_pos[0] = ws->pend_newpos[0];
+      rec->new_pos[1] = ws->pend_newpos[1];
+      rec->new_pos[2] = ws->pend_newpos[2];
+      rec->ratio = ratio;
+      rec->u_acc = ws->pend_uacc;
+      rec->N = ws->pend_N;
+      rec->resid = ws->pend_resid;
+      rec->iters = ws->pend_iters;
+      rec->flags = flags | ((st & WST_SINGULAR) ? VMC_FLAG_SINGULAR : 0);
+    }
+    ws->g += 1;
+    ws->st_steps += 1;
+    if (accept) ws->st_acc += 1;
+    ws->pend_valid = 0;
+    if (st != WST_OK) ws->status |= st;
+  }
+  __threadfence_block();
+  __syncthreads();
+}
+
+}  // namespace vmc

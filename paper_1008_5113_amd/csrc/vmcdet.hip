@@ -1,0 +1,689 @@
+// vmcdet: kernels and the C-ABI entry points (see include/vmcdet.h).
+//
+// Every walker is processed by one workgroup of NT threads; a launch covers a
+// list of walkers (one workgroup each).  The persistent path (vmc_run_steps)
+// keeps each workgroup on its walker for all requested steps, so refactors and
+// reorders of one walker never stall the others.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vmc_step.hpp"
+
+using namespace vmc;
+
+namespace {
+
+constexpr int MODE_BUILD = 1;
+constexpr int MODE_REORDER = 2;
+constexpr int MODE_ILUTP = 4;
+
+__device__ inline Smem setup_smem(char* smem, const Walker& W, const DevParams& P, int ktb) {
+  LdsLayout L = lds_layout(W.n, ktb, P.maxit, P.m_max);
+  return make_smem(smem, L);
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(NT) k_setup(const Walker* __restrict__ walkers, WalkerState* states,
+                                              DevParams P, const int* list, int mode) {
+  extern __shared__ __align__(16) char smem[];
+  const int w = list ? list[blockIdx.x] : (int)blockIdx.x;
+  const Walker& W = walkers[w];
+  Smem S = setup_smem(smem, W, P, PREC == VMC_PREC_FP64 ? 8 : 4);
+  if (threadIdx.x < 32) S.ic[threadIdx.x] = 0;
+  __syncthreads();
+  int st = WST_OK;
+  if (mode & MODE_REORDER) wg_reorder(W, S);
+  if (mode & (MODE_BUILD | MODE_REORDER)) st |= wg_build_all_rows(W, S);
+  if (st == WST_OK && (mode & MODE_ILUTP)) st = wg_ilutp(W, P, S);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    WalkerState* ws = states + w;
+    if (mode & MODE_ILUTP) {
+      ws->m = 0;
+      ws->st_refactors += 1;
+      if (mode & MODE_REORDER) ws->st_reorders += 1;
+    }
+    ws->pend_valid = 0;
+    if (st != WST_OK) ws->status |= st;
+  }
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(NT) k_ratio(const Walker* __restrict__ walkers, WalkerState* states,
+                                              DevParams P, const int* list, const int* particles,
+                                              const double* newpos, vmc_step_record* out) {
+  extern __shared__ __align__(16) char smem[];
+  const int w = list[blockIdx.x];
+  const Walker& W = walkers[w];
+  WalkerState* ws = states + w;
+  Smem S = setup_smem(smem, W, P, PREC == VMC_PREC_FP64 ? 8 : 4);
+  if (threadIdx.x < 32) S.ic[threadIdx.x] = 0;
+  __syncthreads();
+  if (ws->status != WST_OK) {
+    if (threadIdx.x == 0) {
+      out[blockIdx.x].flags = -1;
+      ws->pend_valid = 0;
+    }
+    return;
+  }
+  const long long g = ws->g;
+  double u[4];
+  step_draws(W.seed, g, u);
+  int p;
+  double rnew[3];
+  if (particles) {
+    p = particles[blockIdx.x];
+    rnew[0] = newpos[3 * blockIdx.x];
+    rnew[1] = newpos[3 * blockIdx.x + 1];
+    rnew[2] = newpos[3 * blockIdx.x + 2];
+  } else {
+    p = (int)(g % W.n);
+    for (int c = 0; c < 3; ++c) rnew[c] = propose_axis(W.pos[3 * p + c], u[c], P.step, W.box[c]);
+  }
+  wg_det_ratio<PREC>(W, ws, P, S, p, rnew, u[3]);
+  if (threadIdx.x == 0) {
+    vmc_step_record& r = out[blockIdx.x];
+    r.step = g;
+    r.walker = w;
+    r.particle = p;
+    r.new_pos[0] = rnew[0];
+    r.new_pos[1] = rnew[1];
+    r.new_pos[2] = rnew[2];
+    r.ratio = ws->pend_ratio;
+    r.u_acc = u[3];
+    r.N = ws->pend_N;
+    r.resid = ws->pend_resid;
+    r.iters = ws->pend_iters;
+    r.flags = ws->pend_flags;
+  }
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(NT) k_accept(const Walker* __restrict__ walkers, WalkerState* states,
+                                               DevParams P, const int* list, const unsigned char* decide,
+                                               unsigned char* accepted_out, int* err_out) {
+  extern __shared__ __align__(16) char smem[];
+  const int w = list[blockIdx.x];
+  const Walker& W = walkers[w];
+  WalkerState* ws = states + w;
+  Smem S = setup_smem(smem, W, P, PREC == VMC_PREC_FP64 ? 8 : 4);
+  if (threadIdx.x < 32) S.ic[threadIdx.x] = 0;
+  __syncthreads();
+  if (!ws->pend_valid) {
+    if (threadIdx.x == 0) {
+      err_out[blockIdx.x] = 1;
+      accepted_out[blockIdx.x] = 0;
+    }
+    return;
+  }
+  int acc;
+  if (decide) acc = decide[blockIdx.x] ? 1 : 0;
+  else acc = (ws->pend_ratio * ws->pend_ratio > ws->pend_uacc) ? 1 : 0;
+  wg_accept<PREC>(W, ws, P, S, acc, w, nullptr);
+  if (threadIdx.x == 0) {
+    accepted_out[blockIdx.x] = (unsigned char)acc;
+    err_out[blockIdx.x] = 0;
+  }
+}
+
+// Persistent fused path: `steps` Metropolis steps of one walker per workgroup.
+template <int PREC>
+__global__ void __launch_bounds__(NT) k_run(const Walker* __restrict__ walkers, WalkerState* states,
+                                            DevParams P, int steps, vmc_step_record* log, long long log_cap) {
+  extern __shared__ __align__(16) char smem[];
+  const int w = blockIdx.x;
+  const Walker& W = walkers[w];
+  WalkerState* ws = states + w;
+  Smem S = setup_smem(smem, W, P, PREC == VMC_PREC_FP64 ? 8 : 4);
+  if (threadIdx.x < 32) S.ic[threadIdx.x] = 0;
+  __syncthreads();
+  for (int s = 0; s < steps; ++s) {
+    if (ws->status != WST_OK) break;
+    const long long g = ws->g;
+    double u[4];
+    step_draws(W.seed, g, u);
+    const int p = (int)(g % W.n);
+    double rnew[3];
+    for (int c = 0; c < 3; ++c) rnew[c] = propose_axis(W.pos[3 * p + c], u[c], P.step, W.box[c]);
+    wg_det_ratio<PREC>(W, ws, P, S, p, rnew, u[3]);
+    if (!ws->pend_valid) break;
+    const int acc = (ws->pend_ratio * ws->pend_ratio > u[3]) ? 1 : 0;
+    const long long slot = (long long)w * steps + s;
+    vmc_step_record* rec = (log && slot < log_cap) ? log + slot : nullptr;
+    wg_accept<PREC>(W, ws, P, S, acc, w, rec);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+std::string g_create_error;
+
+struct Ctx {
+  hipStream_t stream = nullptr;
+  vmc_params prm;
+  DevParams dp;
+  int nw = 0;
+  int maxn = 0;
+  int all_same_n = 1;
+  std::vector<Walker> hw;
+  std::vector<void*> arenas;
+  Walker* dW = nullptr;
+  WalkerState* dS = nullptr;
+  size_t lds = 0;
+  // argument staging
+  int* d_list = nullptr;
+  int* d_part = nullptr;
+  double* d_pos = nullptr;
+  vmc_step_record* d_rec = nullptr;
+  unsigned char* d_dec = nullptr;
+  unsigned char* d_acc = nullptr;
+  int* d_err = nullptr;
+  int* d_all = nullptr;
+  std::string err;
+};
+
+#define HIPCHK(ctx, expr)                                                   \
+  do {                                                                      \
+    hipError_t e_ = (expr);                                                 \
+    if (e_ != hipSuccess) {                                                 \
+      (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);       \
+      return VMC_EHIP;                                                      \
+    }                                                                       \
+  } while (0)
+
+int lattice_bound(double radius, double a) {
+  const int K = (int)std::ceil(radius / a);
+  int cnt = 0;
+  for (int x = -K; x <= K; ++x)
+    for (int y = -K; y <= K; ++y)
+      for (int z = -K; z <= K; ++z)
+        if ((double)(x * x + y * y + z * z) * a * a <= radius * radius) ++cnt;
+  return cnt;
+}
+
+template <int PREC>
+vmc_status launch_setup(Ctx* c, const int* dlist, int count, int mode) {
+  hipLaunchKernelGGL(k_setup<PREC>, dim3(count), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, dlist, mode);
+  HIPCHK(c, hipGetLastError());
+  return VMC_OK;
+}
+
+vmc_status stage_list(Ctx* c, const int32_t* walkers, int32_t count, int** dlist) {
+  if (count < 0 || count > c->nw) { c->err = "bad walker count"; return VMC_EINVAL; }
+  if (walkers == nullptr) { *dlist = c->d_all; return VMC_OK; }
+  for (int k = 0; k < count; ++k)
+    if (walkers[k] < 0 || walkers[k] >= c->nw) { c->err = "walker index out of range"; return VMC_EINVAL; }
+  HIPCHK(c, hipMemcpyAsync(c->d_list, walkers, sizeof(int) * count, hipMemcpyHostToDevice, c->stream));
+  *dlist = c->d_list;
+  return VMC_OK;
+}
+
+vmc_status walker_errors(Ctx* c) {
+  std::vector<WalkerState> hs(c->nw);
+  HIPCHK(c, hipMemcpyAsync(hs.data(), c->dS, sizeof(WalkerState) * c->nw, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int w = 0; w < c->nw; ++w) {
+    if (hs[w].status & WST_CAPACITY) { c->err = "walker " + std::to_string(w) + ": capacity exceeded"; return VMC_ECAPACITY; }
+    if (hs[w].status & WST_SINGULAR) { c->err = "walker " + std::to_string(w) + ": singular pivot"; return VMC_ESINGULAR; }
+  }
+  return VMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vmc_status vmc_default_params(vmc_params* p) {
+  if (!p) return VMC_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->precision = VMC_PREC_FP64;
+  p->gmres_maxit = 40;
+  p->gmres_rtol = 1e-10;
+  p->droptol = 1e-4;
+  p->permtol = 0.1;
+  p->lfil = -1;
+  p->m_max = 32;
+  p->n_thresh = 100.0;
+  p->iter_factor = 4.0;
+  p->iter_min_solves = 10;
+  p->inner_rtol = 1e-6;
+  p->refine_tol = 1e-11;
+  p->refine_maxit = 4;
+  p->step = 0.25;
+  p->row_cap = 0;
+  p->force_reorder_every = 0;
+  p->block_threads = 0;
+  return VMC_OK;
+}
+
+vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, const vmc_walker_init* wi,
+                      void* hip_stream) {
+  if (!ctx_out || !p || !wi || n_walkers <= 0) { g_create_error = "invalid arguments"; return VMC_EINVAL; }
+  *ctx_out = nullptr;
+  if (p->precision != VMC_PREC_FP64 && p->precision != VMC_PREC_MIXED) { g_create_error = "bad precision"; return VMC_EINVAL; }
+  if (p->gmres_maxit < 1 || p->gmres_maxit > MAXIT) { g_create_error = "gmres_maxit out of range"; return VMC_EINVAL; }
+  if (p->m_max < 1 || p->m_max > MMAX_CAP) { g_create_error = "m_max out of range"; return VMC_EINVAL; }
+  Ctx* c = new Ctx();
+  c->stream = (hipStream_t)hip_stream;
+  c->prm = *p;
+  c->nw = n_walkers;
+  DevParams& d = c->dp;
+  d.precision = p->precision;
+  d.maxit = p->gmres_maxit;
+  d.rtol = p->gmres_rtol;
+  d.droptol = p->droptol;
+  d.permtol = p->permtol;
+  d.lfil = p->lfil;
+  d.m_max = p->m_max;
+  d.n_thresh = p->n_thresh;
+  d.iter_factor = p->iter_factor;
+  d.iter_min_solves = p->iter_min_solves;
+  d.inner_rtol = p->inner_rtol;
+  d.refine_tol = p->refine_tol;
+  d.refine_maxit = p->refine_maxit;
+  d.step = p->step;
+  d.force_reorder_every = p->force_reorder_every;
+
+  const int ktb = p->precision == VMC_PREC_FP64 ? 8 : 4;
+  auto fail = [&](vmc_status s, const std::string& msg) {
+    g_create_error = msg;
+    for (void* a : c->arenas) (void)hipFree(a);
+    if (c->dW) (void)hipFree(c->dW);
+    if (c->dS) (void)hipFree(c->dS);
+    delete c;
+    return s;
+  };
+  c->hw.resize(n_walkers);
+  for (int w = 0; w < n_walkers; ++w) {
+    const vmc_walker_init& in = wi[w];
+    const int n = in.n;
+    if (n < 1 || n > 16384 || !in.sites || !in.sigma || !in.pos0 || in.a <= 0.0 || in.cutoff <= 0.0)
+      return fail(VMC_EINVAL, "walker " + std::to_string(w) + ": invalid init");
+    if (in.lattice[0] * in.lattice[1] * in.lattice[2] != n)
+      return fail(VMC_EINVAL, "walker " + std::to_string(w) + ": lattice does not match n");
+    if (w > 0 && n != wi[0].n) c->all_same_n = 0;
+    c->maxn = std::max(c->maxn, n);
+    Walker& W = c->hw[w];
+    std::memset(&W, 0, sizeof(W));
+    W.n = n;
+    for (int k = 0; k < 3; ++k) {
+      W.lat[k] = in.lattice[k];
+      W.box[k] = in.lattice[k] * in.a;
+    }
+    W.a = in.a;
+    W.margin = in.site_margin;
+    W.cutoff = in.cutoff;
+    W.kind = in.orbital_kind;
+    W.p_scale = in.p_scale;
+    W.p_sigma = in.p_sigma;
+    W.seed = in.seed;
+    int Wc = p->row_cap > 0 ? p->row_cap
+                            : lattice_bound(in.cutoff + in.site_margin + 0.8660254037844387 * in.a, in.a);
+    Wc = std::min(Wc, n);
+    W.W = Wc;
+    W.F = std::min(n, Wc + (Wc + 1) / 2 + 2);
+    W.UC = 2 * Wc;
+    const int km = p->gmres_maxit;
+    const int mm = p->m_max;
+    // arena layout
+    std::vector<std::pair<void**, size_t>> parts;
+    size_t off = 0;
+    auto add = [&](size_t bytes) {
+      size_t o = off;
+      off = align_up(off + bytes, 256);
+      return o;
+    };
+    const size_t nn = (size_t)n;
+    size_t o_sites = add(nn * 3 * 8), o_sigma = add(nn * 8), o_pos = add(nn * 3 * 8);
+    size_t o_rowperm = add(nn * 4), o_rpos = add(nn * 4), o_cpos = add(nn * 4), o_colsite = add(nn * 4);
+    size_t o_reo_row = add(nn * 4), o_reo_col = add(nn * 4);
+    size_t o_alen = add(nn * 4), o_acol = add(nn * Wc * 4), o_aval = add(nn * Wc * 8), o_aval32 = add(nn * Wc * 4);
+    const size_t F = W.F;
+    size_t o_llen = add(nn * 4), o_lcol = add(nn * F * 4), o_lval = add(nn * F * 8), o_lval32 = add(nn * F * 4);
+    size_t o_ulen = add(nn * 4), o_ucol = add(nn * F * 4), o_uval = add(nn * F * 8), o_udiag = add(nn * 8);
+    size_t o_usval = add(nn * F * 8), o_usval32 = add(nn * F * 4), o_udinv = add(nn * 8), o_udinv32 = add(nn * 4);
+    size_t o_q = add(nn * 4);
+    size_t o_Z64 = p->precision == VMC_PREC_FP64 ? add((size_t)mm * nn * 8) : 0;
+    size_t o_Z32 = p->precision == VMC_PREC_MIXED ? add((size_t)mm * nn * 4) : 0;
+    size_t o_uplen = add((size_t)mm * 4), o_upcol = add((size_t)mm * W.UC * 4), o_upval = add((size_t)mm * W.UC * 8),
+           o_upval32 = add((size_t)mm * W.UC * 4), o_T = add((size_t)mm * mm * 8);
+    size_t o_V = add((size_t)(km + 1) * nn * ktb), o_Xp = add((size_t)km * nn * ktb), o_wv = add(nn * ktb);
+    size_t o_z = add(nn * 8), o_r = add(nn * 8);
+    size_t o_newcol = add((size_t)Wc * 4), o_newval = add((size_t)Wc * 8), o_pucol = add((size_t)W.UC * 4),
+           o_puval = add((size_t)W.UC * 8);
+    void* arena = nullptr;
+    if (hipMalloc(&arena, off) != hipSuccess) return fail(VMC_ENOMEM, "device allocation failed");
+    c->arenas.push_back(arena);
+    if (hipMemset(arena, 0, off) != hipSuccess) return fail(VMC_EHIP, "memset failed");
+    char* b = (char*)arena;
+    W.sites = (const double*)(b + o_sites);
+    W.sigma = (const double*)(b + o_sigma);
+    W.pos = (double*)(b + o_pos);
+    W.rowperm = (int*)(b + o_rowperm);
+    W.rpos = (int*)(b + o_rpos);
+    W.cpos = (int*)(b + o_cpos);
+    W.colsite = (int*)(b + o_colsite);
+    W.reo_row = (int*)(b + o_reo_row);
+    W.reo_col = (int*)(b + o_reo_col);
+    W.a_len = (int*)(b + o_alen);
+    W.a_col = (int*)(b + o_acol);
+    W.a_val = (double*)(b + o_aval);
+    W.a_val32 = (float*)(b + o_aval32);
+    W.l_len = (int*)(b + o_llen);
+    W.l_col = (int*)(b + o_lcol);
+    W.l_val = (double*)(b + o_lval);
+    W.l_val32 = (float*)(b + o_lval32);
+    W.u_len = (int*)(b + o_ulen);
+    W.u_col = (int*)(b + o_ucol);
+    W.u_val = (double*)(b + o_uval);
+    W.u_diag = (double*)(b + o_udiag);
+    W.us_val = (double*)(b + o_usval);
+    W.us_val32 = (float*)(b + o_usval32);
+    W.u_dinv = (double*)(b + o_udinv);
+    W.u_dinv32 = (float*)(b + o_udinv32);
+    W.ilu_q = (int*)(b + o_q);
+    W.Z64 = p->precision == VMC_PREC_FP64 ? (double*)(b + o_Z64) : nullptr;
+    W.Z32 = p->precision == VMC_PREC_MIXED ? (float*)(b + o_Z32) : nullptr;
+    W.up_len = (int*)(b + o_uplen);
+    W.up_col = (int*)(b + o_upcol);
+    W.up_val = (double*)(b + o_upval);
+    W.up_val32 = (float*)(b + o_upval32);
+    W.T = (double*)(b + o_T);
+    W.V = (void*)(b + o_V);
+    W.Xp = (void*)(b + o_Xp);
+    W.wv = (void*)(b + o_wv);
+    W.zvec = (double*)(b + o_z);
+    W.rvec = (double*)(b + o_r);
+    W.new_col = (int*)(b + o_newcol);
+    W.new_val = (double*)(b + o_newval);
+    W.pu_col = (int*)(b + o_pucol);
+    W.pu_val = (double*)(b + o_puval);
+    // host-side initial data
+    std::vector<int> ident(n);
+    for (int k = 0; k < n; ++k) ident[k] = k;
+    bool ok = true;
+    ok &= hipMemcpy((void*)W.sites, in.sites, nn * 3 * 8, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemcpy((void*)W.sigma, in.sigma, nn * 8, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemcpy(W.pos, in.pos0, nn * 3 * 8, hipMemcpyHostToDevice) == hipSuccess;
+    for (int* dst : {W.rowperm, W.rpos, W.cpos, W.colsite, W.reo_row, W.reo_col, W.ilu_q})
+      ok &= hipMemcpy(dst, ident.data(), nn * 4, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) return fail(VMC_EHIP, "initial copy failed");
+  }
+  if (hipMalloc(&c->dW, sizeof(Walker) * n_walkers) != hipSuccess ||
+      hipMalloc(&c->dS, sizeof(WalkerState) * n_walkers) != hipSuccess)
+    return fail(VMC_ENOMEM, "device allocation failed");
+  (void)hipMemcpy(c->dW, c->hw.data(), sizeof(Walker) * n_walkers, hipMemcpyHostToDevice);
+  (void)hipMemset(c->dS, 0, sizeof(WalkerState) * n_walkers);
+  // staging buffers
+  std::vector<int> all(n_walkers);
+  for (int k = 0; k < n_walkers; ++k) all[k] = k;
+  bool ok = hipMalloc(&c->d_list, sizeof(int) * n_walkers) == hipSuccess;
+  ok &= hipMalloc(&c->d_all, sizeof(int) * n_walkers) == hipSuccess;
+  ok &= hipMalloc(&c->d_part, sizeof(int) * n_walkers) == hipSuccess;
+  ok &= hipMalloc(&c->d_pos, sizeof(double) * 3 * n_walkers) == hipSuccess;
+  ok &= hipMalloc(&c->d_rec, sizeof(vmc_step_record) * n_walkers) == hipSuccess;
+  ok &= hipMalloc(&c->d_dec, n_walkers) == hipSuccess;
+  ok &= hipMalloc(&c->d_acc, n_walkers) == hipSuccess;
+  ok &= hipMalloc(&c->d_err, sizeof(int) * n_walkers) == hipSuccess;
+  if (!ok) return fail(VMC_ENOMEM, "device allocation failed");
+  (void)hipMemcpy(c->d_all, all.data(), sizeof(int) * n_walkers, hipMemcpyHostToDevice);
+
+  LdsLayout L = lds_layout(c->maxn, ktb, p->gmres_maxit, p->m_max);
+  c->lds = L.total;
+  int dev = 0, maxlds = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (maxlds > 0 && (int)c->lds > maxlds) {
+    return fail(VMC_EINVAL, "n too large: needs " + std::to_string(c->lds) + " bytes of LDS per workgroup, device has " +
+                                std::to_string(maxlds));
+  }
+  if (p->precision == VMC_PREC_FP64) {
+    (void)hipFuncSetAttribute((const void*)k_setup<VMC_PREC_FP64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
+    (void)hipFuncSetAttribute((const void*)k_ratio<VMC_PREC_FP64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
+    (void)hipFuncSetAttribute((const void*)k_accept<VMC_PREC_FP64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
+    (void)hipFuncSetAttribute((const void*)k_run<VMC_PREC_FP64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
+  } else {
+    (void)hipFuncSetAttribute((const void*)k_setup<VMC_PREC_MIXED>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
+    (void)hipFuncSetAttribute((const void*)k_ratio<VMC_PREC_MIXED>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
+    (void)hipFuncSetAttribute((const void*)k_accept<VMC_PREC_MIXED>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
+    (void)hipFuncSetAttribute((const void*)k_run<VMC_PREC_MIXED>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
+  }
+  if (hipDeviceSynchronize() != hipSuccess) return fail(VMC_EHIP, "device synchronize failed");
+  *ctx_out = c;
+  return VMC_OK;
+}
+
+vmc_status vmc_build_slater(void* ctx, const int32_t* walkers, int32_t count) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c) return VMC_EINVAL;
+  if (!walkers) count = c->nw;
+  int* dl = nullptr;
+  vmc_status s = stage_list(c, walkers, count, &dl);
+  if (s) return s;
+  if (count == 0) return VMC_OK;
+  s = c->dp.precision == VMC_PREC_FP64 ? launch_setup<VMC_PREC_FP64>(c, dl, count, MODE_BUILD)
+                                       : launch_setup<VMC_PREC_MIXED>(c, dl, count, MODE_BUILD);
+  if (s) return s;
+  return walker_errors(c);
+}
+
+vmc_status vmc_ilutp(void* ctx, const int32_t* walkers, int32_t count, int32_t reorder) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c) return VMC_EINVAL;
+  if (!walkers) count = c->nw;
+  int* dl = nullptr;
+  vmc_status s = stage_list(c, walkers, count, &dl);
+  if (s) return s;
+  if (count == 0) return VMC_OK;
+  const int mode = MODE_ILUTP | (reorder ? MODE_REORDER : 0);
+  s = c->dp.precision == VMC_PREC_FP64 ? launch_setup<VMC_PREC_FP64>(c, dl, count, mode)
+                                       : launch_setup<VMC_PREC_MIXED>(c, dl, count, mode);
+  if (s) return s;
+  return walker_errors(c);
+}
+
+vmc_status vmc_det_ratio(void* ctx, const int32_t* walkers, int32_t count, const int32_t* particle,
+                         const double* new_pos, double* ratio_out, vmc_step_record* info_out) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || !ratio_out || count < 0) return VMC_EINVAL;
+  if (!walkers) count = c->nw;
+  if ((particle == nullptr) != (new_pos == nullptr)) { c->err = "particle and new_pos go together"; return VMC_EINVAL; }
+  int* dl = nullptr;
+  vmc_status s = stage_list(c, walkers, count, &dl);
+  if (s) return s;
+  if (count == 0) return VMC_OK;
+  if (particle) {
+    for (int k = 0; k < count; ++k) {
+      const int w = walkers ? walkers[k] : k;
+      const Walker& W = c->hw[w];
+      if (particle[k] < 0 || particle[k] >= W.n) { c->err = "particle out of range"; return VMC_EINVAL; }
+      for (int a = 0; a < 3; ++a) {
+        const double x = new_pos[3 * k + a];
+        if (!(x >= 0.0 && x < W.box[a])) { c->err = "new_pos outside the box"; return VMC_EINVAL; }
+      }
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_part, particle, sizeof(int) * count, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_pos, new_pos, sizeof(double) * 3 * count, hipMemcpyHostToDevice, c->stream));
+  }
+  if (c->dp.precision == VMC_PREC_FP64)
+    hipLaunchKernelGGL(k_ratio<VMC_PREC_FP64>, dim3(count), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, dl,
+                       particle ? c->d_part : nullptr, particle ? c->d_pos : nullptr, c->d_rec);
+  else
+    hipLaunchKernelGGL(k_ratio<VMC_PREC_MIXED>, dim3(count), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, dl,
+                       particle ? c->d_part : nullptr, particle ? c->d_pos : nullptr, c->d_rec);
+  HIPCHK(c, hipGetLastError());
+  std::vector<vmc_step_record> rec(count);
+  HIPCHK(c, hipMemcpyAsync(rec.data(), c->d_rec, sizeof(vmc_step_record) * count, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < count; ++k) {
+    ratio_out[k] = rec[k].ratio;
+    if (info_out) info_out[k] = rec[k];
+  }
+  s = walker_errors(c);
+  if (s) return s;
+  for (int k = 0; k < count; ++k)
+    if (!(rec[k].flags & VMC_FLAG_CONVERGED)) { c->err = "GMRES did not converge after reorder"; return VMC_ENOCONV; }
+  return VMC_OK;
+}
+
+vmc_status vmc_accept(void* ctx, const int32_t* walkers, int32_t count, const uint8_t* accept,
+                      uint8_t* accepted_out) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || count < 0) return VMC_EINVAL;
+  if (!walkers) count = c->nw;
+  int* dl = nullptr;
+  vmc_status s = stage_list(c, walkers, count, &dl);
+  if (s) return s;
+  if (count == 0) return VMC_OK;
+  if (accept) HIPCHK(c, hipMemcpyAsync(c->d_dec, accept, count, hipMemcpyHostToDevice, c->stream));
+  if (c->dp.precision == VMC_PREC_FP64)
+    hipLaunchKernelGGL(k_accept<VMC_PREC_FP64>, dim3(count), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, dl,
+                       accept ? c->d_dec : nullptr, c->d_acc, c->d_err);
+  else
+    hipLaunchKernelGGL(k_accept<VMC_PREC_MIXED>, dim3(count), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, dl,
+                       accept ? c->d_dec : nullptr, c->d_acc, c->d_err);
+  HIPCHK(c, hipGetLastError());
+  std::vector<unsigned char> acc(count);
+  std::vector<int> err(count);
+  HIPCHK(c, hipMemcpyAsync(acc.data(), c->d_acc, count, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(err.data(), c->d_err, sizeof(int) * count, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (accepted_out) std::memcpy(accepted_out, acc.data(), count);
+  for (int k = 0; k < count; ++k)
+    if (err[k]) { c->err = "accept without a pending ratio"; return VMC_ESTATE; }
+  return walker_errors(c);
+}
+
+vmc_status vmc_run_steps(void* ctx, int32_t steps, vmc_step_record* dev_log, int64_t log_cap) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || steps < 0) return VMC_EINVAL;
+  if (steps == 0) return VMC_OK;
+  if (c->dp.precision == VMC_PREC_FP64)
+    hipLaunchKernelGGL(k_run<VMC_PREC_FP64>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, steps,
+                       dev_log, (long long)(dev_log ? log_cap : 0));
+  else
+    hipLaunchKernelGGL(k_run<VMC_PREC_MIXED>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, steps,
+                       dev_log, (long long)(dev_log ? log_cap : 0));
+  HIPCHK(c, hipGetLastError());
+  return VMC_OK;
+}
+
+vmc_status vmc_run_sweeps(void* ctx, int32_t sweeps, vmc_step_record* dev_log, int64_t log_cap) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || sweeps < 0) return VMC_EINVAL;
+  if (!c->all_same_n) { c->err = "vmc_run_sweeps needs walkers of equal n; use vmc_run_steps"; return VMC_EINVAL; }
+  const long long steps = (long long)sweeps * c->hw[0].n;
+  if (steps > 0x7fffffffLL) { c->err = "too many steps"; return VMC_EINVAL; }
+  return vmc_run_steps(ctx, (int32_t)steps, dev_log, log_cap);
+}
+
+vmc_status vmc_sync(void* ctx) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c) return VMC_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return walker_errors(c);
+}
+
+vmc_status vmc_get_dims(void* ctx, int32_t walker, int32_t* n, int32_t* row_cap, int32_t* fact_cap) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || walker < 0 || walker >= c->nw) return VMC_EINVAL;
+  if (n) *n = c->hw[walker].n;
+  if (row_cap) *row_cap = c->hw[walker].W;
+  if (fact_cap) *fact_cap = c->hw[walker].F;
+  return VMC_OK;
+}
+
+vmc_status vmc_get_state(void* ctx, int32_t walker, const vmc_state_view* v) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || !v || walker < 0 || walker >= c->nw) return VMC_EINVAL;
+  const Walker& W = c->hw[walker];
+  const size_t n = W.n;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  auto cp = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    if (!dst) return hipSuccess;
+    return hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost);
+  };
+  HIPCHK(c, cp(v->pos, W.pos, n * 3 * 8));
+  HIPCHK(c, cp(v->row_particle, W.rowperm, n * 4));
+  HIPCHK(c, cp(v->col_site, W.colsite, n * 4));
+  HIPCHK(c, cp(v->reorder_row, W.reo_row, n * 4));
+  HIPCHK(c, cp(v->reorder_col, W.reo_col, n * 4));
+  HIPCHK(c, cp(v->a_len, W.a_len, n * 4));
+  HIPCHK(c, cp(v->a_col, W.a_col, n * W.W * 4));
+  HIPCHK(c, cp(v->a_val, W.a_val, n * W.W * 8));
+  HIPCHK(c, cp(v->l_len, W.l_len, n * 4));
+  HIPCHK(c, cp(v->l_col, W.l_col, n * W.F * 4));
+  HIPCHK(c, cp(v->l_val, W.l_val, n * W.F * 8));
+  HIPCHK(c, cp(v->u_len, W.u_len, n * 4));
+  HIPCHK(c, cp(v->u_col, W.u_col, n * W.F * 4));
+  HIPCHK(c, cp(v->u_val, W.u_val, n * W.F * 8));
+  HIPCHK(c, cp(v->u_diag, W.u_diag, n * 8));
+  HIPCHK(c, cp(v->ilu_perm, W.ilu_q, n * 4));
+  if (v->step || v->n_updates) {
+    WalkerState s;
+    HIPCHK(c, hipMemcpy(&s, c->dS + walker, sizeof(s), hipMemcpyDeviceToHost));
+    if (v->step) *v->step = s.g;
+    if (v->n_updates) *v->n_updates = s.m;
+  }
+  return VMC_OK;
+}
+
+vmc_status vmc_get_stats(void* ctx, vmc_stats* out) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || !out) return VMC_EINVAL;
+  std::vector<WalkerState> hs(c->nw);
+  HIPCHK(c, hipMemcpyAsync(hs.data(), c->dS, sizeof(WalkerState) * c->nw, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int w = 0; w < c->nw; ++w) {
+    const WalkerState& s = hs[w];
+    vmc_stats& o = out[w];
+    std::memset(&o, 0, sizeof(o));
+    o.steps = s.st_steps;
+    o.accepted = s.st_acc;
+    o.solves = s.st_solves;
+    o.iters = s.st_iters;
+    o.reorders = s.st_reorders;
+    o.refactors = s.st_refactors;
+    o.nonconverged = s.st_nonconv;
+    o.inner_solves = s.st_inner;
+    o.refine_passes = s.st_refine;
+    o.max_N = s.st_maxN;
+    o.sum_N = s.st_sumN;
+    o.status = (s.status & WST_CAPACITY) ? VMC_ECAPACITY : (s.status & WST_SINGULAR) ? VMC_ESINGULAR : VMC_OK;
+  }
+  return VMC_OK;
+}
+
+const char* vmc_last_error(void* ctx) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c) return g_create_error.c_str();
+  return c->err.c_str();
+}
+
+vmc_status vmc_destroy(void* ctx) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c) return VMC_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  for (void* a : c->arenas) (void)hipFree(a);
+  (void)hipFree(c->dW);
+  (void)hipFree(c->dS);
+  (void)hipFree(c->d_list);
+  (void)hipFree(c->d_all);
+  (void)hipFree(c->d_part);
+  (void)hipFree(c->d_pos);
+  (void)hipFree(c->d_rec);
+  (void)hipFree(c->d_dec);
+  (void)hipFree(c->d_acc);
+  (void)hipFree(c->d_err);
+  delete c;
+  return VMC_OK;
+}
+
+}  // extern "C"

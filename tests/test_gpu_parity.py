@@ -1,0 +1,222 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle.chain import StepRecord, replay
+from oracle.geometry import orbital_values, slater_dense
+from oracle.ilutp import dense_factors, ilutp, paper_lfil, rows_from_dense
+from oracle.ratio import ratio_lu
+from oracle.reorder import geometric_reorder
+
+pytestmark = pytest.mark.gpu
+
+DLOG_TOL = 1e-10      # |ln|ratio_gpu| - ln|ratio_oracle||
+DEC_TOL = 1e-9        # decisions may differ only where |ratio^2 - u| <= DEC_TOL
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def vm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1008_5113_amd as vm
+    vm.lib()  # fails loudly when the library is missing
+    return vm
+
+
+def _dense_from_state(st, n):
+    D = np.zeros((n, n))
+    for i in range(n):
+        L = st["a_len"][i]
+        D[i, st["a_col"][i, :L]] = st["a_val"][i, :L]
+    return D
+
+
+def _records(log_row):
+    return [StepRecord(int(r["step"]), int(r["particle"]), np.array(r["new_pos"]), float(r["ratio"]),
+                       float(r["u_acc"]), bool(r["flags"] & 1)) for r in log_row]
+
+
+def test_build_pattern_bitexact(vm):
+    _say("case: build pattern plain_n128")
+    inst = wl.plain_n128()
+    s = inst.systems[0]
+    ctx = vm.Context.from_instance(inst)
+    ctx.build_slater()
+    st = ctx.state(0)
+    n = s.n
+    A_or = slater_dense(inst.walkers[0].pos0, s)
+    D = _dense_from_state(st, n)
+    D_or = A_or[st["row_particle"]][:, st["col_site"]]
+    assert np.array_equal(D != 0, D_or != 0)
+    nz = D_or != 0
+    assert np.max(np.abs(D[nz] - D_or[nz]) / np.abs(D_or[nz])) < 1e-14
+    ctx.close()
+
+
+@pytest.mark.parametrize("lattice,cutoff,kind", [((4, 4, 8), 2.0, 0), ((6, 6, 6), 2.5, 1)])
+def test_reorder_bitexact(vm, lattice, cutoff, kind):
+    _say(f"case: reorder {lattice}")
+    inst = wl.small_instance(lattice=lattice, cutoff=cutoff, kind=kind, p_scale=0.1 if kind else 0.0,
+                             n_walkers=2, jitter=0.45)
+    s = inst.systems[0]
+    ctx = vm.Context.from_instance(inst)
+    ctx.ilutp(reorder=True)
+    for w in range(2):
+        st = ctx.state(w)
+        row, col = geometric_reorder(inst.walkers[w].pos0, s)
+        assert np.array_equal(st["reorder_row"], row)
+        assert np.array_equal(st["reorder_col"], col)
+    ctx.close()
+
+
+def test_reorder_exact_matching_configuration(vm):
+    _say("case: reorder exact matching")
+    s = wl.make_system((4, 4, 8), cutoff=2.0)
+    rng = np.random.default_rng(11)
+    pi = rng.permutation(s.n)
+    pos = s.sites[pi].copy()
+    p = vm.default_params()
+    ctx = vm.Context([s], [(0, pos, 0)], p)
+    ctx.ilutp(reorder=True)
+    st = ctx.state(0)
+    row, col = geometric_reorder(pos, s)
+    assert np.array_equal(st["reorder_row"], row) and np.array_equal(st["reorder_col"], col)
+    assert np.array_equal(col, pi[row])
+    ctx.close()
+
+
+def test_ilutp_against_oracle(vm):
+    _say("case: ilutp plain_n128")
+    inst = wl.plain_n128()
+    s = inst.systems[0]
+    ctx = vm.Context.from_instance(inst)
+    ctx.ilutp(reorder=True)
+    st = ctx.state(0, factors=True)
+    n = s.n
+    # A after the factorisation is stored with the ILU permutation folded into its
+    # columns: D = A_reordered Q.  Undo Q to get the matrix that was factored.
+    D = _dense_from_state(st, n)
+    q = st["ilu_perm"]
+    A_fact = np.zeros_like(D)
+    A_fact[:, q] = D
+    rows = rows_from_dense(A_fact)
+    nnz = sum(len(r) for r in rows)
+    L, U, qo = ilutp(rows, n, 1e-4, 0.1, paper_lfil(nnz, n))
+    assert np.array_equal(q, qo)
+    Lo, Uo = dense_factors(L, U, n)
+    Lg = np.eye(n)
+    Ug = np.diag(st["u_diag"])
+    for i in range(n):
+        Lg[i, st["l_col"][i, :st["l_len"][i]]] = st["l_val"][i, :st["l_len"][i]]
+        Ug[i, st["u_col"][i, :st["u_len"][i]]] = st["u_val"][i, :st["u_len"][i]]
+    assert np.max(np.abs(Lg - Lo)) < 1e-12
+    assert np.max(np.abs(Ug - Uo)) < 1e-12
+    assert np.linalg.norm(D - Lg @ Ug) / np.linalg.norm(D) < 1e-3
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_explicit_moves_ratio(vm, precision):
+    _say(f"case: explicit moves precision={precision}")
+    inst = wl.plain_n128()
+    s = inst.systems[0]
+    ctx = vm.Context.from_instance(inst, precision=precision)
+    ctx.ilutp(reorder=True)
+    pos = inst.walkers[0].pos0.copy()
+    A = slater_dense(pos, s)
+    rng = np.random.default_rng(4)
+    for k in range(20):
+        p = int(rng.integers(0, s.n))
+        rnew = (pos[p] + rng.uniform(-0.3, 0.3, 3)) % s.box
+        ratio, info = ctx.det_ratio(walkers=[0], particles=[p], new_pos=rnew[None, :])
+        r_or, _ = ratio_lu(A, p, orbital_values(rnew, s))
+        assert abs(np.log(abs(ratio[0])) - np.log(abs(r_or))) < DLOG_TOL, (k, ratio[0], r_or)
+        acc = k % 2 == 0
+        ctx.accept(walkers=[0], decisions=[acc])
+        if acc:
+            A[p] = orbital_values(rnew, s)
+            pos[p] = rnew
+    st = ctx.state(0)
+    assert np.array_equal(st["pos"], pos)
+    ctx.close()
+
+
+def test_unmoved_and_back_move(vm):
+    _say("case: unmoved / back-move")
+    inst = wl.plain_n128()
+    ctx = vm.Context.from_instance(inst)
+    ctx.ilutp(reorder=True)
+    pos = inst.walkers[0].pos0
+    r, _ = ctx.det_ratio(walkers=[0], particles=[5], new_pos=pos[5][None, :])
+    assert r[0] == 1.0
+    ctx.accept(walkers=[0], decisions=[False])
+    rnew = (pos[5] + np.array([0.2, -0.15, 0.1])) % inst.systems[0].box
+    r1, _ = ctx.det_ratio(walkers=[0], particles=[5], new_pos=rnew[None, :])
+    ctx.accept(walkers=[0], decisions=[True])
+    r2, _ = ctx.det_ratio(walkers=[0], particles=[5], new_pos=pos[5][None, :])
+    ctx.accept(walkers=[0], decisions=[False])
+    assert abs(r1[0] * r2[0] - 1.0) < 1e-10
+    ctx.close()
+
+
+def _free_run_check(vm, inst, steps, precision, walkers=(0,), **kw):
+    s = inst.systems[0]
+    ctx = vm.Context.from_instance(inst, walkers=list(walkers), precision=precision, **kw)
+    ctx.ilutp(reorder=True)
+    log = ctx.run_steps_logged(steps)
+    out = []
+    for k, w in enumerate(walkers):
+        recs = _records(log[k])
+        mode = "lu" if s.n <= 256 else "sm"
+        rep = replay(s, inst.walkers[w].pos0, inst.walkers[w].seed, inst.params.step, recs,
+                     dec_tol=DEC_TOL, mode=mode)
+        out.append((rep, log[k]))
+    stats = ctx.stats()
+    ctx.close()
+    return out, stats
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_free_run_plain_n128(vm, precision):
+    _say(f"case: free run plain_n128 precision={precision}")
+    inst = wl.plain_n128()
+    steps = 4 * inst.systems[0].n
+    (res,), stats = _free_run_check(vm, inst, steps, precision)
+    rep, log = res
+    _say(f"  max dlog {rep.max_dlog:.3e} acc {np.mean(log['flags'] & 1):.3f} "
+         f"iters {np.mean(log['iters']):.2f} stats {stats[0]}")
+    assert rep.pos_mismatch == 0
+    assert rep.sign_mismatch == 0
+    assert rep.decision_mismatch_outside_tol == 0
+    assert rep.max_dlog < DLOG_TOL
+    assert np.all(log["flags"] & 8)
+
+
+def test_forced_triggers(vm):
+    _say("case: forced triggers")
+    inst = wl.plain_n128()
+    # reorder + refactor every 7th step, refactor after every 3 updates
+    (res,), stats = _free_run_check(vm, inst, 300, 0, force_reorder_every=7, m_max=3)
+    rep, log = res
+    assert rep.pos_mismatch == 0 and rep.decision_mismatch_outside_tol == 0
+    assert rep.max_dlog < DLOG_TOL
+    assert np.sum(log["flags"] & 2) > 0 and np.sum(log["flags"] & 4) > 0
+    assert stats[0]["reorders"] >= 300 // 7
+
+
+def test_batch_fp64_n1024_subset(vm):
+    _say("case: batch fp64_n1024 4 walkers")
+    inst = wl.fp64_n1024(4)
+    outs, stats = _free_run_check(vm, inst, 300, 0, walkers=(0, 1, 2, 3))
+    for rep, log in outs:
+        assert rep.pos_mismatch == 0 and rep.decision_mismatch_outside_tol == 0
+        assert rep.max_dlog < DLOG_TOL
