@@ -1,0 +1,291 @@
+"""Benchmark: determinant-ratio steps/s of the persistent fused HIP path.
+
+One bench "step" is one Metropolis step of every walker in the batch (proposal,
+Slater row, ILUTP-preconditioned GMRES ratio, decision, row replacement,
+preconditioner update, and any triggered reorder/refactor), i.e. `walkers`
+det-ratio steps.  The timed region is one launch of the persistent kernel
+covering K such steps, bracketed by device synchronisations and timed with
+events on the stream the kernel runs on.  Set-up (context creation, initial
+reorder and ILUTP) and W warm-up steps are outside the timed region.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "det-ratio steps/s, n=4000 x 512 walkers, mixed vs FP64 GMRES; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# Algorithmic bytes of the method per timed region:
+# every GMRES iteration streams A, L and U once (values + 4-byte indices), the
+# stored update vectors once, and a handful of n-vectors; a mixed-precision
+# refinement pass streams A in FP64 once.
+# ---------------------------------------------------------------------------
+def algorithmic_bytes(stats0, stats1, nnz, n, mixed: bool):
+    sv = 4 if mixed else 8
+    nA, nL, nU = nnz
+    tot = 0.0
+    for a, b in zip(stats0, stats1):
+        iters = b["iters"] - a["iters"]
+        inner = b["inner_solves"] - a["inner_solves"]
+        solves = b["solves"] - a["solves"]
+        passes = b["refine_passes"] - a["refine_passes"]
+        msum = b["update_sum"] - a["update_sum"]
+        m_avg = msum / inner if inner else 0.0
+        per_iter = (nA + nL + nU) * (sv + 4) + n * sv * (1 + m_avg) + 4 * n * sv
+        tot += iters * per_iter
+        tot += inner * (n * 8)                   # solution accumulation write
+        if mixed:
+            tot += (solves + passes) * (nA * (8 + 4) + n * 16)
+    return tot
+
+
+def factor_nnz(ctx, walkers):
+    acc = np.zeros(3)
+    for w in walkers:
+        st = ctx.state(w, factors=True)
+        acc += [st["a_len"].sum(), st["l_len"].sum(), st["u_len"].sum() + len(st["u_len"])]
+    return acc / len(walkers)
+
+
+def run_path(inst, precision, steps, warmup, walkers, stream_ptr, **kw):
+    import torch
+    import paper_1008_5113_amd as vm
+    t0 = time.time()
+    ctx = vm.Context.from_instance(inst, walkers=walkers, precision=precision, stream=stream_ptr, **kw)
+    ctx.ilutp(reorder=True)
+    ctx.sync()
+    log(f"precision={precision}: set-up (create + reorder + ILUTP of {len(walkers)} walkers) "
+        f"{time.time() - t0:.1f}s")
+    if warmup:
+        t1 = time.time()
+        ctx.run_steps(warmup)
+        ctx.sync()
+        log(f"precision={precision}: warm-up {warmup} steps {time.time() - t1:.1f}s")
+    s0 = ctx.stats()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    ctx.run_steps(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    ctx.sync()
+    s1 = ctx.stats()
+    nnz = factor_nnz(ctx, list(range(min(4, len(walkers)))))
+    n = ctx.ns[0]
+    bytes_ = algorithmic_bytes(s0, s1, nnz, n, precision == vm.PREC_MIXED)
+    d = lambda k: sum(b[k] - a[k] for a, b in zip(s0, s1))  # noqa: E731
+    nsteps = d("steps")
+    ph = np.zeros(12)
+    for a, b in zip(s0, s1):
+        ph += np.array(b["phase_ticks"], dtype=np.float64) - np.array(a["phase_ticks"], dtype=np.float64)
+    phase_us = {name: ph[k] / max(1, nsteps) / vm.vmcdet.WALL_CLOCK_HZ * 1e6
+                for k, name in enumerate(vm.vmcdet.PHASE_NAMES)}
+    out = dict(
+        ms=ms, steps=nsteps, steps_per_s=nsteps / (ms / 1e3),
+        accept=d("accepted") / max(1, nsteps), iters_per_step=d("iters") / max(1, nsteps),
+        inner_per_step=d("inner_solves") / max(1, nsteps), passes_per_step=d("refine_passes") / max(1, nsteps),
+        reorders=d("reorders"), refactors=d("refactors"), nonconverged=d("nonconverged"),
+        max_N=max(b["max_N"] for b in s1), nnz_per_row=(nnz / n).tolist(),
+        phase_us_per_walker_step={k: round(v, 2) for k, v in phase_us.items()},
+        alg_bytes=bytes_, alg_gbs=bytes_ / (ms / 1e3) / 1e9,
+        status=[b["status"] for b in s1 if b["status"] != 0][:4])
+    ctx.close()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle's standard algorithm (explicit inverse with
+# Sherman-Morrison updates), one walker per process, set-up untimed.
+# ---------------------------------------------------------------------------
+def _oracle_worker(args):
+    workload, w, steps = args
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        import workloads as wl
+        from oracle.geometry import orbital_values, propose, slater_dense
+        from oracle.ratio import StandardAlgorithm
+        from oracle.rng import step_draws
+        inst = wl.WORKLOADS[workload](w + 1)
+        s = inst.systems[0]
+        wk = inst.walkers[w]
+        pos = wk.pos0.copy()
+        sm = StandardAlgorithm(slater_dense(pos, s))
+        t0 = time.perf_counter()
+        for g in range(steps):
+            p = g % s.n
+            u = step_draws(wk.seed, g)
+            rnew = propose(pos[p], u[:3], inst.params.step, s.box)
+            row = orbital_values(rnew, s)
+            ratio = sm.ratio(p, row)
+            if ratio * ratio > u[3]:
+                sm.accept(p, row, ratio)
+                pos[p] = rnew
+        return steps, time.perf_counter() - t0
+
+
+def cpu_baseline(workload, procs, steps):
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(procs) as pool:
+        res = pool.map(_oracle_worker, [(workload, w, steps) for w in range(procs)])
+    wall = time.perf_counter() - t0
+    tot = sum(r[0] for r in res)
+    loop = max(r[1] for r in res)
+    return dict(value=tot / loop, unit="det-ratio steps/s", cores=procs, kind="oracle",
+                sample=f"{workload}: walkers 0..{procs - 1}, {steps} steps each, one process per walker "
+                       f"(single-threaded BLAS), standard algorithm (explicit inverse + Sherman-Morrison); "
+                       f"inverse set-up untimed; wall {wall:.1f}s")
+
+
+def phase_bench(inst, precision, walkers, stream_ptr, reps, warm_steps, **kw):
+    """Per-phase micro-benchmarks at the workload's real shapes (one launch per
+    phase, every walker's workgroup repeating the phase `reps` times)."""
+    import torch
+    import paper_1008_5113_amd as vm
+    ctx = vm.Context.from_instance(inst, walkers=walkers, precision=precision, stream=stream_ptr, **kw)
+    ctx.ilutp(reorder=True)
+    if warm_steps:
+        ctx.run_steps(warm_steps)
+    ctx.sync()
+    nnz = factor_nnz(ctx, list(range(min(4, len(walkers)))))
+    n = ctx.ns[0]
+    m_avg = float(np.mean([ctx.state(w)["n_updates"] for w in range(min(8, len(walkers)))]))
+    nA, nL, nU = nnz
+    sv = 4 if precision == vm.PREC_MIXED else 8
+    per_rep = {
+        "spmv": nA * (sv + 4) + n * (4 + sv),
+        "lsolve": (nL) * (sv + 4) + n * 4,
+        "usolve": (nU - n) * (sv + 4) + n * (4 + sv),
+        "updates": m_avg * n * sv,
+        "resid64": nA * 12 + n * (4 + 8 + 8),
+    }
+    out = {"m_avg": m_avg, "nnz_per_row": (nnz / n).tolist()}
+    stream = torch.cuda.current_stream()
+    for ph in ["spmv", "lsolve", "usolve", "updates", "resid64"]:
+        if ph == "resid64" and precision != vm.PREC_MIXED:
+            continue
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        ctx.phase_bench(ph, reps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        b = per_rep[ph] * reps * len(walkers)
+        out[ph] = {"ms": ms, "us_per_rep": ms * 1e3 / reps, "alg_gbs": b / (ms / 1e3) / 1e9,
+                   "frac_hbm": b / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+        log(f"phase {ph}: {out[ph]}")
+    ctx.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--workload", default="mixed_n4000")
+    ap.add_argument("--walkers", type=int, default=0, help="0: the workload's count")
+    ap.add_argument("--paths", default="mixed,fp64")
+    ap.add_argument("--m-max", type=int, default=0, help="stored updates before a refactor (0: workload)")
+    ap.add_argument("--cpu-procs", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--phases", action="store_true", help="per-phase micro-benchmarks only")
+    ap.add_argument("--phase-reps", type=int, default=20)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}))
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: walkers are independent chains and this build "
+              "measures one GPU's share; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as wl
+    import paper_1008_5113_amd as vm
+    torch.cuda.set_device(0)
+    inst = wl.WORKLOADS[args.workload]() if not args.walkers else wl.WORKLOADS[args.workload](args.walkers)
+    nw = len(inst.walkers)
+    walkers = list(range(nw))
+    stream_ptr = torch.cuda.current_stream().cuda_stream
+    if args.phases:
+        res = {}
+        for path in args.paths.split(","):
+            prec = vm.PREC_MIXED if path == "mixed" else vm.PREC_FP64
+            kw = {"m_max": args.m_max} if args.m_max else {}
+            res[path] = phase_bench(inst, prec, walkers, stream_ptr, args.phase_reps, args.warmup, **kw)
+        print(json.dumps({"phases": res, "workload": args.workload, "walkers": nw}))
+        return
+    results = {}
+    for path in args.paths.split(","):
+        prec = vm.PREC_MIXED if path == "mixed" else vm.PREC_FP64
+        log(f"path {path}: {nw} walkers, n={inst.systems[0].n}, {args.steps} timed steps")
+        kw = {"m_max": args.m_max} if args.m_max else {}
+        results[path] = run_path(inst, prec, args.steps, args.warmup, walkers, stream_ptr, **kw)
+        log(f"path {path}: {json.dumps(results[path])}")
+    head = results.get("mixed") or results[next(iter(results))]
+    headpath = "mixed" if "mixed" in results else next(iter(results))
+    out = {
+        "metric": METRIC,
+        "value": head["steps_per_s"],
+        "unit": "det-ratio steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if headpath == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": inst.systems[0].n, "walkers": nw,
+                   "lattice": "x".join(str(x) for x in inst.systems[0].lattice),
+                   "path": headpath, "step": "one Metropolis step of every walker"},
+        "paths": results,
+    }
+    if "mixed" in results and "fp64" in results:
+        out["mixed_over_fp64"] = results["mixed"]["steps_per_s"] / results["fp64"]["steps_per_s"]
+    out["roofline"] = {"bound": "hbm", "achieved": head["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": head["alg_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                       "kernel": "k_run (persistent fused step kernel)"}
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: {args.cpu_procs} processes x {args.cpu_steps} oracle steps")
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_procs, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

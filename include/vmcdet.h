@@ -145,6 +145,10 @@ typedef struct vmc_state_view {
 typedef struct vmc_stats {
   int64_t steps, accepted, solves, iters, reorders, refactors, nonconverged;
   int64_t inner_solves, refine_passes;
+  int64_t update_sum;       /* sum over inner solves of the stored updates applied */
+  int64_t phase_ticks[12];  /* device wall-clock ticks per phase: prepare, L solve, U solve,
+                               updates, SpMV, orthogonalisation, solution, FP64 residual,
+                               accept, refactor, reorder, whole persistent launch */
   double max_N, sum_N;
   int32_t status;           /* VMC_OK or the first error the walker hit */
   int32_t pad;
@@ -196,6 +200,13 @@ vmc_status vmc_run_steps(void* ctx, int32_t steps, vmc_step_record* dev_log, int
 /* vmc_run_steps with steps = sweeps * n of each walker (a sweep moves every
    particle once); requires all walkers to share n.  Asynchronous. */
 vmc_status vmc_run_sweeps(void* ctx, int32_t sweeps, vmc_step_record* dev_log, int64_t log_cap);
+
+/* Diagnostic micro-benchmark: every walker's workgroup runs one phase of the
+   solve `reps` times on its current matrix and factors, in one launch:
+   0 SpMV (solve precision), 1 forward solve with L, 2 backward solve with U,
+   3 rank-one update application, 4 FP64 residual e_i - A z, 5 ILUTP.
+   Phases 0-4 leave the walker state unchanged; 5 refactors.  Asynchronous. */
+vmc_status vmc_phase_bench(void* ctx, int32_t phase, int32_t reps);
 
 /* Wait for all work issued on the context's stream; returns the first walker
    error (if any) as a status. */

@@ -18,27 +18,26 @@ __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a -
 
 __host__ __device__ inline size_t ilutp_lds_bytes(int n) {
   size_t b = 0;
-  b += align_up((size_t)n * 8, 16);        // wv
-  b += align_up((size_t)n, 16);            // present flags
-  b += align_up((size_t)n * 2, 16);        // pinv
-  b += align_up((size_t)n * 2, 16);        // q
-  b += align_up((size_t)NZMAX * 2, 16);    // work-row column list
-  b += align_up((size_t)LMAX * 2, 16);     // multiplier positions
-  b += align_up((size_t)LMAX * 8, 16);     // multiplier values
+  b += align_up((size_t)n * 8, 16);              // wv: dense work row
+  b += align_up((size_t)(n + 31) / 32 * 4, 16);  // presence bitmap
+  b += align_up((size_t)n * 2, 16);              // pinv
+  b += align_up((size_t)n * 2, 16);              // q
+  b += align_up((size_t)NZMAX * 2, 16);          // work-row column list
+  b += align_up((size_t)LMAX * 2, 16);           // multiplier positions
+  b += align_up((size_t)LMAX * 8, 16);           // multiplier values
+  b += (size_t)ilu_cmax(n) * 8 + align_up((size_t)ilu_cmax(n) * 2, 16) * 3;  // candidate tables
+  b += align_up((size_t)SCAP * 2, 16);           // staged U-row columns
+  b += (size_t)SCAP * 8;                         // staged U-row values
   return b;
 }
 
+// Region A (phase union): the solve phase holds the triangular-solve vector,
+// the in-block coefficient tile, the GMRES scalars and the update
+// coefficients; the ILUTP and reorder phases reuse the same bytes.  Region B
+// (reduction slots and broadcast scalars) is live in every phase.
 __host__ __device__ inline LdsLayout lds_layout(int n, int ktb, int maxit, int mmax) {
   LdsLayout L;
-  size_t solve = align_up((size_t)n, 4) * ktb + (size_t)BLK * BLK * ktb;
-  size_t ilu = ilutp_lds_bytes(n);
-  size_t reo = align_up((size_t)n * 2, 16) * 2;
-  size_t a = solve;
-  if (ilu > a) a = ilu;
-  if (reo > a) a = reo;
-  size_t o = align_up(a, 16);
-  L.regionA = 0;
-  L.red = o; o += (size_t)NWAVE * (MAXIT + 2) * 8;
+  size_t o = align_up((size_t)n, 4) * ktb + (size_t)BLK * BLK * ktb;  // xs, D
   L.hb = o; o += (MAXIT + 2) * 8;
   L.cs = o; o += (MAXIT + 1) * 8;
   L.sn = o; o += (MAXIT + 1) * 8;
@@ -47,6 +46,14 @@ __host__ __device__ inline LdsLayout lds_layout(int n, int ktb, int maxit, int m
   L.yb = o; o += (MAXIT + 1) * 8;
   L.gb = o; o += (size_t)(mmax + 1) * 8;
   L.cb = o; o += (size_t)(mmax + 1) * 8;
+  size_t a = o;
+  const size_t ilu = ilutp_lds_bytes(n);
+  const size_t reo = align_up((size_t)n * 2, 16) * 2;
+  if (ilu > a) a = ilu;
+  if (reo > a) a = reo;
+  o = align_up(a, 16);
+  L.regionA = 0;
+  L.red = o; o += (size_t)NWAVE * (MAXIT + 2) * 8;
   L.sc = o; o += 32 * 8;
   L.ic = o; o += 32 * 4;
   L.stmp = o; o += BLK * 8;
@@ -68,6 +75,7 @@ struct Smem {
   double* sc;
   int* ic;
   void* stmp;
+  unsigned long long* ph;
 };
 
 __device__ inline Smem make_smem(char* base, const LdsLayout& L) {
@@ -85,8 +93,22 @@ __device__ inline Smem make_smem(char* base, const LdsLayout& L) {
   s.sc = (double*)(base + L.sc);
   s.ic = (int*)(base + L.ic);
   s.stmp = (void*)(base + L.stmp);
+  s.ph = nullptr;
   return s;
 }
+
+// Phase timer: thread 0 adds the wall-clock ticks between two points.
+struct PhaseClock {
+  unsigned long long t;
+  __device__ inline void start() { t = wall_clock64(); }
+  __device__ inline void stop(const Smem& S, int ph) {
+    if (S.ph && threadIdx.x == 0) {
+      const unsigned long long now = wall_clock64();
+      S.ph[ph] += now - t;
+      t = now;
+    }
+  }
+};
 
 // ---------------------------------------------------------------------------
 // Reductions (deterministic: fixed butterfly order, identical in every lane)
@@ -94,37 +116,82 @@ __device__ inline Smem make_smem(char* base, const LdsLayout& L) {
 __device__ inline int lane_id() { return threadIdx.x & 63; }
 __device__ inline int wave_id() { return threadIdx.x >> 6; }
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// DPP lane moves (VALU, no LDS traffic).  quad_perm xor 1 / xor 2 and the
+// row mirrors stay inside a 16-lane row; row_shl:4 reads lane+4 of the row.
+constexpr int DPP_QXOR1 = 0xB1;       // quad_perm:[1,0,3,2]
+constexpr int DPP_QXOR2 = 0x4E;       // quad_perm:[2,3,0,1]
+constexpr int DPP_HMIRROR = 0x141;    // row_half_mirror
+constexpr int DPP_MIRROR = 0x140;     // row_mirror
+constexpr int DPP_SHL4 = 0x104;       // row_shl:4
+
+template <int CTRL>
+__device__ inline int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
 }
-__device__ inline float wave_sumf(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+template <int CTRL>
+__device__ inline float dpp_f(float v) {
+  return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
 }
-__device__ inline int wave_sumi(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const int lo = dpp_i<CTRL>(__double2loint(v));
+  const int hi = dpp_i<CTRL>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
 }
+template <int CTRL> __device__ inline double dpp_t(double v) { return dpp_d<CTRL>(v); }
+template <int CTRL> __device__ inline float dpp_t(float v) { return dpp_f<CTRL>(v); }
+template <int CTRL> __device__ inline int dpp_t(int v) { return dpp_i<CTRL>(v); }
+
+__device__ inline double readlane_d(double v, int k) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline float readlane_f(float v, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+__device__ inline int readlane_i(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
+__device__ inline double readlane_t(double v, int k) { return readlane_d(v, k); }
+__device__ inline float readlane_t(float v, int k) { return readlane_f(v, k); }
+__device__ inline int readlane_t(int v, int k) { return readlane_i(v, k); }
+
+// Sum over the 64 lanes; every lane gets the same value (fixed order).
+template <typename T>
+__device__ inline T wave_sum_t(T v) {
+  v += dpp_t<DPP_QXOR1>(v);
+  v += dpp_t<DPP_QXOR2>(v);
+  v += dpp_t<DPP_HMIRROR>(v);
+  v += dpp_t<DPP_MIRROR>(v);
+  return (readlane_t(v, 0) + readlane_t(v, 16)) + (readlane_t(v, 32) + readlane_t(v, 48));
+}
+__device__ inline double wave_sum(double v) { return wave_sum_t(v); }
+__device__ inline float wave_sumf(float v) { return wave_sum_t(v); }
+__device__ inline int wave_sumi(int v) { return wave_sum_t(v); }
 __device__ inline int wave_mini(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-  return v;
+  v = min(v, dpp_i<DPP_QXOR1>(v));
+  v = min(v, dpp_i<DPP_QXOR2>(v));
+  v = min(v, dpp_i<DPP_HMIRROR>(v));
+  v = min(v, dpp_i<DPP_MIRROR>(v));
+  return min(min(readlane_i(v, 0), readlane_i(v, 16)), min(readlane_i(v, 32), readlane_i(v, 48)));
 }
 __device__ inline double wave_maxd(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
 }
-// sum over groups of 8 consecutive lanes
+// Sum over groups of 8 consecutive lanes; the total is valid in lanes 8k.
 template <typename T>
 __device__ inline T sum8(T v) {
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
-  v += __shfl_xor(v, 4, 64);
+  v += dpp_t<DPP_QXOR1>(v);
+  v += dpp_t<DPP_QXOR2>(v);
+  v += dpp_t<DPP_SHL4>(v);
+  return v;
+}
+// Sum over groups of 4 consecutive lanes; valid in every lane of the group.
+template <typename T>
+__device__ inline T sum4(T v) {
+  v += dpp_t<DPP_QXOR1>(v);
+  v += dpp_t<DPP_QXOR2>(v);
   return v;
 }
 

@@ -12,9 +12,21 @@ constexpr int NT = 512;        // threads per walker workgroup
 constexpr int NWAVE = NT / 64;
 constexpr int BLK = 64;        // rows per triangular-solve block (one lane per row)
 constexpr int MAXIT = 64;      // largest supported GMRES iteration count
-constexpr int NZMAX = 2048;    // ILUTP work-row entry capacity
-constexpr int LMAX = 1024;     // ILUTP multipliers per row before the fill limit
+constexpr int NZMAX = 512;     // ILUTP work-row entry capacity
+constexpr int LMAX = 256;      // ILUTP multipliers per row before the fill limit
+constexpr int CMAX = 384;      // ILUTP elimination candidates per row (large n)
+
+// Candidate capacity: small systems can be nearly dense, large lattices are
+// bounded by the orbital stencil.
+__host__ __device__ inline int ilu_cmax(int n) { return n <= 1024 ? (n < 512 ? n : 512) : CMAX; }
+constexpr int SCAP = 880;      // ILUTP staged U-row entries per row
 constexpr int MMAX_CAP = 256;  // largest supported m_max
+
+// In-kernel phase timers (wall-clock ticks, accumulated by thread 0).
+enum Phase {
+  PH_PREPARE = 0, PH_LSOLVE, PH_USOLVE, PH_UPDATES, PH_SPMV, PH_ORTHO, PH_SOLUTION, PH_RESID,
+  PH_ACCEPT, PH_REFACTOR, PH_REORDER, PH_STEP, PH_COUNT
+};
 
 // Walker-level error codes stored on the device (mapped to vmc_status on the host).
 constexpr int WST_OK = 0;
@@ -121,8 +133,9 @@ struct WalkerState {
   long long avg_count;
   // counters
   long long st_steps, st_acc, st_solves, st_iters, st_reorders, st_refactors, st_nonconv;
-  long long st_inner, st_refine;
+  long long st_inner, st_refine, st_msum;
   double st_maxN, st_sumN;
+  unsigned long long ph[PH_COUNT];
 };
 
 }  // namespace vmc

@@ -24,16 +24,8 @@ template <> struct Fac<float> {
   __device__ static const float* upval(const Walker& W) { return W.up_val32; }
 };
 
-__device__ inline float readlane_k(float v, int k) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
-}
-__device__ inline double readlane_k(double v, int k) {
-  int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
-  int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
-  return __hiloint2double(hi, lo);
-}
 
-constexpr int PF = 8;  // entries per thread held in registers per block (8 threads per row)
+constexpr int PF = 4;  // entries per thread held in registers per block (8 threads per row)
 
 // One 64-row block of a triangular factor, as seen by one of the 8 threads of a row.
 template <typename KT>
@@ -41,12 +33,13 @@ struct RowChunk {
   int len;
   int col[PF];
   KT val[PF];
+  KT aux;  // right-hand side (L) or inverse diagonal (U) of the row
 };
 
 template <typename KT>
 __device__ inline void load_chunk(RowChunk<KT>& ch, int r, int n, int len, const int* cols,
                                   const KT* vals, int F, int sub) {
-  ch.len = (r < n) ? len : 0;
+  ch.len = (r >= 0 && r < n) ? len : 0;
 #pragma unroll
   for (int t = 0; t < PF; ++t) {
     const int e = sub + 8 * t;
@@ -58,180 +51,215 @@ __device__ inline void load_chunk(RowChunk<KT>& ch, int r, int n, int len, const
 }
 
 // In-block substitution by wave 0: lane r holds the block right-hand side of
-// row r; D (LDS, column-major 64x64) holds the in-block coefficients and is
-// cleared as it is read.  Forward (unit lower) or backward (unit upper).
+// row r; D (LDS, column-major 64x64) holds the in-block coefficients.  Step k
+// broadcasts x_k from lane k (v_readlane) and every lane subtracts its
+// coefficient times x_k.  The coefficients are read in batches of 16 that are
+// issued one batch ahead of use, so LDS latency stays off the dependency chain.
 template <typename KT, bool FORWARD>
-__device__ inline KT block_chain(KT a, KT* D) {
+__device__ inline KT block_chain(KT a, const KT* D) {
+  constexpr int B = sizeof(KT) == 8 ? 8 : 16;  // coefficients per batch (register budget)
   const int lane = lane_id();
-  if (FORWARD) {
-#pragma unroll 16
-    for (int k = 0; k < BLK; ++k) {
-      const KT dk = D[k * BLK + lane];
-      D[k * BLK + lane] = (KT)0;
-      const KT xk = readlane_k(a, k);
-      a -= dk * xk;
+  KT d0[B], d1[B];
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    const int k = FORWARD ? j : BLK - 1 - j;
+    d0[j] = D[k * BLK + lane];
+  }
+#pragma unroll
+  for (int q = 0; q < BLK / B; ++q) {
+    if (q + 1 < BLK / B) {
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        const int k = FORWARD ? B * (q + 1) + j : BLK - 1 - (B * (q + 1) + j);
+        d1[j] = D[k * BLK + lane];
+      }
     }
-  } else {
-#pragma unroll 16
-    for (int k = BLK - 1; k >= 0; --k) {
-      const KT dk = D[k * BLK + lane];
-      D[k * BLK + lane] = (KT)0;
-      const KT xk = readlane_k(a, k);
-      a -= dk * xk;
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const int k = FORWARD ? B * q + j : BLK - 1 - (B * q + j);
+      const KT xk = readlane_t(a, k);
+      a -= d0[j] * xk;
     }
+#pragma unroll
+    for (int j = 0; j < B; ++j) d0[j] = d1[j];
   }
   return a;
 }
 
-// Forward solve L x = b with unit lower L (rows by position, capacity F).
-// b = rhs (global) or, when rhs == nullptr, the unit vector e_unit.
-// Blocks of 64 rows: 8 threads per row gather the contributions of columns in
-// earlier blocks from x (LDS) and scatter in-block coefficients into D; wave 0
-// then runs the in-block chain.  Row data of the next block is loaded into
-// registers while the current block is processed.
-template <typename KT>
-__device__ inline void wg_lsolve(const Walker& W, const KT* lval, const KT* rhs, int unit, KT* xs,
-                                 KT* D, KT* st) {
+// Triangular solve by 64-row blocks.  FORWARD: L x = b with unit lower L, b =
+// rhs (global) or e_unit when rhs == nullptr.  Backward: U x = y in place on
+// xs, with U stored as D^{-1}U (unit upper, off-diagonal) and D^{-1}.
+// 8 threads per row gather the contributions of columns in already-solved
+// blocks from xs (LDS) and scatter in-block coefficients into D; wave 0 then
+// runs the in-block chain.  Row data is loaded two blocks ahead of use and
+// row lengths three blocks ahead, so the loads of later blocks are in flight
+// while the current block's chain runs.
+template <typename KT, bool FORWARD>
+__device__ inline void wg_trisolve(const Walker& W, const int* lens, const int* cols, const KT* vals,
+                                   const KT* aux, int unit, KT* xs, KT* D, KT* st) {
   const int n = W.n, F = W.F;
   const int rr = threadIdx.x >> 3, sub = threadIdx.x & 7;
   const int nb = (n + BLK - 1) / BLK;
-  RowChunk<KT> cur, nxt;
-  KT crhs = 0, nrhs = 0;
-  int nlen2 = 0;
+  // block index sequence: 0..nb-1 forward, nb-1..0 backward
+  auto blk = [&](int t) { return FORWARD ? t : nb - 1 - t; };
+  auto row_of = [&](int t) { return (t >= 0 && t < nb) ? blk(t) * BLK + rr : -1; };
+  auto len_of = [&](int t) {
+    const int r = row_of(t);
+    return (r >= 0 && r < n) ? lens[r] : 0;
+  };
+  auto aux_of = [&](int r) -> KT {
+    if (r < 0 || r >= n) return (KT)0;
+    if (FORWARD) return aux ? aux[r] : (KT)(r == unit ? 1 : 0);
+    return aux[r];
+  };
+  RowChunk<KT> c0, c1, c2;
   {
-    const int r = rr;
-    load_chunk(cur, r, n, r < n ? W.l_len[r] : 0, W.l_col, lval, F, sub);
-    crhs = (r < n) ? (rhs ? rhs[r] : (KT)(r == unit ? 1 : 0)) : (KT)0;
-    const int r1 = BLK + rr;
-    nlen2 = (r1 < n) ? W.l_len[r1] : 0;
+    const int la = len_of(0), lb = len_of(1);
+    load_chunk(c0, row_of(0), n, la, cols, vals, F, sub);
+    c0.aux = aux_of(row_of(0));
+    load_chunk(c1, row_of(1), n, lb, cols, vals, F, sub);
+    c1.aux = aux_of(row_of(1));
   }
-  for (int b = 0; b < nb; ++b) {
-    const int r0 = b * BLK;
+  int len2 = len_of(2);
+  for (int t = 0; t < nb; ++t) {
+    const int r0 = blk(t) * BLK;
     const int r = r0 + rr;
-    // prefetch block b+1 (its lengths were loaded one block earlier) and lengths of b+2
-    if (b + 1 < nb) {
-      const int r1 = r + BLK;
-      load_chunk(nxt, r1, n, nlen2, W.l_col, lval, F, sub);
-      nrhs = (r1 < n) ? (rhs ? rhs[r1] : (KT)(r1 == unit ? 1 : 0)) : (KT)0;
-      const int r2 = r + 2 * BLK;
-      nlen2 = (r2 < n) ? W.l_len[r2] : 0;
-    }
+    // prefetch block t+2 and the row lengths of block t+3
+    load_chunk(c2, row_of(t + 2), n, len2, cols, vals, F, sub);
+    c2.aux = aux_of(row_of(t + 2));
+    len2 = len_of(t + 3);
     KT acc = 0;
+    int dpos[PF];
 #pragma unroll
-    for (int t = 0; t < PF; ++t) {
-      const int e = sub + 8 * t;
-      if (e < cur.len) {
-        const int c = cur.col[t];
-        if (c < r0) acc += cur.val[t] * xs[c];
-        else D[(c - r0) * BLK + rr] = cur.val[t];
+    for (int k = 0; k < PF; ++k) {
+      const int e = sub + 8 * k;
+      dpos[k] = -1;
+      if (e < c0.len) {
+        const int c = c0.col[k];
+        const bool far = FORWARD ? (c < r0) : (c >= r0 + BLK);
+        if (far) {
+          acc += c0.val[k] * xs[c];
+        } else {
+          dpos[k] = (c - r0) * BLK + rr;
+          D[dpos[k]] = c0.val[k];
+        }
       }
     }
-    for (int e = sub + 8 * PF; e < cur.len; e += 8) {
-      const int c = W.l_col[(size_t)r * F + e];
-      const KT v = lval[(size_t)r * F + e];
-      if (c < r0) acc += v * xs[c];
+    for (int e = sub + 8 * PF; e < c0.len; e += 8) {
+      const int c = cols[(size_t)r * F + e];
+      const KT v = vals[(size_t)r * F + e];
+      const bool far = FORWARD ? (c < r0) : (c >= r0 + BLK);
+      if (far) acc += v * xs[c];
       else D[(c - r0) * BLK + rr] = v;
     }
     acc = sum8(acc);
-    if (sub == 0) st[rr] = crhs - acc;
+    if (sub == 0) {
+      KT b;
+      if (FORWARD) b = c0.aux;
+      else b = (r < n) ? xs[r] * c0.aux : (KT)0;
+      st[rr] = b - acc;
+    }
     __syncthreads();
     if (wave_id() == 0) {
       KT a = st[lane_id()];
-      a = block_chain<KT, true>(a, D);
+      a = block_chain<KT, FORWARD>(a, D);
       if (r0 + lane_id() < n) xs[r0 + lane_id()] = a;
     }
     __syncthreads();
-    cur = nxt;
-    crhs = nrhs;
+    // D back to zero: every thread clears the coefficients it scattered (the
+    // next block's scatter comes later in the same wave's program order)
+#pragma unroll
+    for (int k = 0; k < PF; ++k)
+      if (dpos[k] >= 0) D[dpos[k]] = (KT)0;
+    for (int e = sub + 8 * PF; e < c0.len; e += 8) {
+      const int c = cols[(size_t)r * F + e];
+      const bool far = FORWARD ? (c < r0) : (c >= r0 + BLK);
+      if (!far) D[(c - r0) * BLK + rr] = (KT)0;
+    }
+    c0 = c1;
+    c1 = c2;
   }
 }
 
-// Backward solve with U, stored as D^{-1}U (unit upper, off-diagonal) and
-// D^{-1}; in place on xs.
+template <typename KT>
+__device__ inline void wg_lsolve(const Walker& W, const KT* lval, const KT* rhs, int unit, KT* xs,
+                                 KT* D, KT* st) {
+  wg_trisolve<KT, true>(W, W.l_len, W.l_col, lval, rhs, unit, xs, D, st);
+}
+
 template <typename KT>
 __device__ inline void wg_usolve(const Walker& W, const KT* usval, const KT* dinv, KT* xs, KT* D,
                                  KT* st) {
-  const int n = W.n, F = W.F;
-  const int rr = threadIdx.x >> 3, sub = threadIdx.x & 7;
-  const int nb = (n + BLK - 1) / BLK;
-  RowChunk<KT> cur, nxt;
-  KT cd = 0, nd = 0;
-  int nlen2 = 0;
-  {
-    const int r = (nb - 1) * BLK + rr;
-    load_chunk(cur, r, n, r < n ? W.u_len[r] : 0, W.u_col, usval, F, sub);
-    cd = (r < n) ? dinv[r] : (KT)0;
-    const int r1 = r - BLK;
-    nlen2 = (r1 >= 0 && r1 < n) ? W.u_len[r1] : 0;
-  }
-  for (int b = nb - 1; b >= 0; --b) {
-    const int r0 = b * BLK;
-    const int r = r0 + rr;
-    if (b > 0) {
-      const int r1 = r - BLK;
-      load_chunk(nxt, r1, n, nlen2, W.u_col, usval, F, sub);
-      nd = (r1 < n) ? dinv[r1] : (KT)0;
-      const int r2 = r - 2 * BLK;
-      nlen2 = (r2 >= 0 && r2 < n) ? W.u_len[r2] : 0;
-    }
-    const int rend = r0 + BLK;
-    KT acc = 0;
-#pragma unroll
-    for (int t = 0; t < PF; ++t) {
-      const int e = sub + 8 * t;
-      if (e < cur.len) {
-        const int c = cur.col[t];
-        if (c >= rend) acc += cur.val[t] * xs[c];
-        else D[(c - r0) * BLK + rr] = cur.val[t];
-      }
-    }
-    for (int e = sub + 8 * PF; e < cur.len; e += 8) {
-      const int c = W.u_col[(size_t)r * F + e];
-      const KT v = usval[(size_t)r * F + e];
-      if (c >= rend) acc += v * xs[c];
-      else D[(c - r0) * BLK + rr] = v;
-    }
-    acc = sum8(acc);
-    if (sub == 0) st[rr] = (r < n) ? xs[r] * cd - acc : (KT)0;
-    __syncthreads();
-    if (wave_id() == 0) {
-      KT a = st[lane_id()];
-      a = block_chain<KT, false>(a, D);
-      if (r0 + lane_id() < n) xs[r0 + lane_id()] = a;
-    }
-    __syncthreads();
-    cur = nxt;
-    cd = nd;
-  }
+  wg_trisolve<KT, false>(W, W.u_len, W.u_col, usval, dinv, -1, xs, D, st);
 }
 
 // x <- (I - zhat_{m-1} u_{m-1}^T) ... (I - zhat_0 u_0^T) x, in the compact form
 // c = G g with g_s = u_s^T x and G = (I + T)^{-1}, T_{st} = u_s^T zhat_t (t < s).
+// g: 4 threads per update vector; c: one thread per update; the x update
+// reads four stored vectors per pass with every thread's rows in registers.
 template <typename KT>
 __device__ inline void wg_updates(const Walker& W, int m, int mmax, KT* xs, Smem& S) {
   if (m <= 0) return;
   const int n = W.n;
   const KT* upv = Fac<KT>::upval(W);
-  for (int s = wave_id(); s < m; s += NWAVE) {
-    const int len = W.up_len[s];
+  for (int s0 = 0; s0 < m; s0 += NT / 4) {
+    const int s = s0 + (threadIdx.x >> 2), part = threadIdx.x & 3;
     KT acc = 0;
-    for (int e = lane_id(); e < len; e += 64)
-      acc += upv[(size_t)s * W.UC + e] * xs[W.up_col[(size_t)s * W.UC + e]];
-    const double sacc = wave_sum((double)acc);
-    if (lane_id() == 0) S.gb[s] = sacc;
+    if (s < m) {
+      const int len = W.up_len[s];
+      const int* uc = W.up_col + (size_t)s * W.UC;
+      const KT* uv = upv + (size_t)s * W.UC;
+#pragma unroll 4
+      for (int e = part; e < len; e += 4) acc += uv[e] * xs[uc[e]];
+    }
+    acc = sum4(acc);
+    if (s < m && part == 0) S.gb[s] = (double)acc;
   }
   __syncthreads();
   for (int s = threadIdx.x; s < m; s += NT) {
+    const double* Gs = W.T + (size_t)s * mmax;
     double c = 0.0;
-    for (int t = 0; t <= s; ++t) c += W.T[(size_t)s * mmax + t] * S.gb[t];
+#pragma unroll 8
+    for (int t = 0; t <= s; ++t) c += Gs[t] * S.gb[t];
     S.cb[s] = c;
   }
   __syncthreads();
   const KT* Z = Fac<KT>::Z(W);
-  for (int r = threadIdx.x; r < n; r += NT) {
-    KT v = xs[r];
-    for (int s = 0; s < m; ++s) v -= Z[(size_t)s * n + r] * (KT)S.cb[s];
-    xs[r] = v;
+  constexpr int RPT = 8;  // rows per thread held in registers
+  for (int rb = 0; rb < n; rb += NT * RPT) {
+    KT xr[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int r = rb + k * NT + threadIdx.x;
+      xr[k] = (r < n) ? xs[r] : (KT)0;
+    }
+    int s = 0;
+    for (; s + 4 <= m; s += 4) {
+      const KT c0 = (KT)S.cb[s], c1 = (KT)S.cb[s + 1], c2 = (KT)S.cb[s + 2], c3 = (KT)S.cb[s + 3];
+      const KT* z0 = Z + (size_t)s * n;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int r = rb + k * NT + threadIdx.x;
+        if (r < n) {
+          const KT a0 = z0[r], a1 = z0[n + r], a2 = z0[2 * (size_t)n + r], a3 = z0[3 * (size_t)n + r];
+          xr[k] -= a0 * c0 + a1 * c1 + a2 * c2 + a3 * c3;
+        }
+      }
+    }
+    for (; s < m; ++s) {
+      const KT c0 = (KT)S.cb[s];
+      const KT* z0 = Z + (size_t)s * n;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int r = rb + k * NT + threadIdx.x;
+        if (r < n) xr[k] -= z0[r] * c0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int r = rb + k * NT + threadIdx.x;
+      if (r < n) xs[r] = xr[k];
+    }
   }
   __syncthreads();
 }
@@ -243,53 +271,130 @@ __device__ inline void wg_precond(const Walker& W, int m, int mmax, const KT* vi
                                   Smem& S) {
   KT* D = xs + align_up((size_t)W.n, 4);
   KT* st = (KT*)S.stmp;
+  PhaseClock pc;
+  pc.start();
   wg_lsolve<KT>(W, Fac<KT>::lval(W), vin, unit, xs, D, st);
+  pc.stop(S, PH_LSOLVE);
   wg_usolve<KT>(W, Fac<KT>::usval(W), Fac<KT>::dinv(W), xs, D, st);
+  pc.stop(S, PH_USOLVE);
   wg_updates<KT>(W, m, mmax, xs, S);
+  pc.stop(S, PH_UPDATES);
 }
 
-// w = A x with x in LDS; 8 threads per row.
+// Sparse row dot products for the SpMV: 8 threads per row, each thread owning
+// a contiguous chunk of SPMV_CH entries read with 16-byte loads (row starts
+// are 16-byte aligned because the row capacity is a multiple of 4); entries
+// past 8*SPMV_CH fall to a strided tail loop.  Rows shorter than the chunk
+// origin issue no loads, so the bytes read follow the row lengths.
+constexpr int SPMV_CH = 12;
+
+template <typename VT>
+__device__ inline void load_vals4(const VT* p, VT* v);
+template <>
+__device__ inline void load_vals4<float>(const float* p, float* v) {
+  const float4 t = *reinterpret_cast<const float4*>(p);
+  v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+}
+template <>
+__device__ inline void load_vals4<double>(const double* p, double* v) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+
+// acc = sum over the thread's chunk of row (ac, av, len) of av[e] * x[ac[e]]
+template <typename VT, typename XT, typename AT>
+__device__ inline AT row_chunk_dot(const int* ac, const VT* av, int len, int sub, const XT* x) {
+  const int e0 = sub * SPMV_CH;
+  AT acc = 0;
+  if (e0 < len) {
+    int c[SPMV_CH];
+    VT v[SPMV_CH];
+#pragma unroll
+    for (int p = 0; p < SPMV_CH / 4; ++p) {
+      if (e0 + 4 * p < len) {
+        const int4 t = *reinterpret_cast<const int4*>(ac + e0 + 4 * p);
+        c[4 * p] = t.x; c[4 * p + 1] = t.y; c[4 * p + 2] = t.z; c[4 * p + 3] = t.w;
+        load_vals4<VT>(av + e0 + 4 * p, v + 4 * p);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { c[4 * p + k] = 0; v[4 * p + k] = 0; }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < SPMV_CH; ++t)
+      if (e0 + t < len) acc += (AT)v[t] * (AT)x[c[t]];
+  }
+  for (int e = 8 * SPMV_CH + sub; e < len; e += 8) acc += (AT)av[e] * (AT)x[ac[e]];
+  return acc;
+}
+
+// w = A x (x in LDS or global), two rows per thread group per pass, row
+// lengths loaded one pass ahead.  When out_resid is set, writes e_unit - A x
+// instead and returns the partial sum of squares.
+template <typename VT, typename XT, typename AT, typename OT>
+__device__ inline double wg_rows_apply(const Walker& W, const VT* aval, const XT* x, OT* out, int unit,
+                                       bool resid) {
+  const int n = W.n, Wc = W.W;
+  const int rr = threadIdx.x >> 3, sub = threadIdx.x & 7;
+  double sq = 0.0;
+  int l0 = (rr < n) ? W.a_len[rr] : 0;
+  int l1 = (rr + BLK < n) ? W.a_len[rr + BLK] : 0;
+  for (int base = 0; base < n; base += 2 * BLK) {
+    const int r0 = base + rr, r1 = r0 + BLK;
+    const int len0 = l0, len1 = l1;
+    l0 = (r0 + 2 * BLK < n) ? W.a_len[r0 + 2 * BLK] : 0;
+    l1 = (r1 + 2 * BLK < n) ? W.a_len[r1 + 2 * BLK] : 0;
+    AT a0 = (r0 < n) ? row_chunk_dot<VT, XT, AT>(W.a_col + (size_t)r0 * Wc, aval + (size_t)r0 * Wc, len0, sub, x) : (AT)0;
+    AT a1 = (r1 < n) ? row_chunk_dot<VT, XT, AT>(W.a_col + (size_t)r1 * Wc, aval + (size_t)r1 * Wc, len1, sub, x) : (AT)0;
+    a0 = sum8(a0);
+    a1 = sum8(a1);
+    if (sub == 0) {
+      if (r0 < n) {
+        if (resid) {
+          const double y = (r0 == unit ? 1.0 : 0.0) - (double)a0;
+          out[r0] = (OT)y;
+          sq += y * y;
+        } else {
+          out[r0] = (OT)a0;
+        }
+      }
+      if (r1 < n) {
+        if (resid) {
+          const double y = (r1 == unit ? 1.0 : 0.0) - (double)a1;
+          out[r1] = (OT)y;
+          sq += y * y;
+        } else {
+          out[r1] = (OT)a1;
+        }
+      }
+    }
+  }
+  return sq;
+}
+
+// w = A x with x in LDS.
 template <typename KT>
 __device__ inline void wg_spmv(const Walker& W, const KT* aval, const KT* xs, KT* w) {
-  const int n = W.n, Wc = W.W;
-  const int rr = threadIdx.x >> 3, sub = threadIdx.x & 7;
-  for (int base = 0; base < n; base += BLK) {
-    const int r = base + rr;
-    KT acc = 0;
-    if (r < n) {
-      const int len = W.a_len[r];
-      const int* ac = W.a_col + (size_t)r * Wc;
-      const KT* av = aval + (size_t)r * Wc;
-      for (int e = sub; e < len; e += 8) acc += av[e] * xs[ac[e]];
-    }
-    acc = sum8(acc);
-    if (sub == 0 && r < n) w[r] = acc;
-  }
+  wg_rows_apply<KT, KT, KT, KT>(W, aval, xs, w, -1, false);
 }
 
-// r = e_unit - A z in FP64 (z global); returns ||r||_2.
-__device__ inline double wg_resid64(const Walker& W, const double* z, int unit, double* rv, Smem& S) {
-  const int n = W.n, Wc = W.W;
-  const int rr = threadIdx.x >> 3, sub = threadIdx.x & 7;
-  double nl = 0.0;
-  for (int base = 0; base < n; base += BLK) {
-    const int r = base + rr;
-    double acc = 0.0;
-    if (r < n) {
-      const int len = W.a_len[r];
-      const int* ac = W.a_col + (size_t)r * Wc;
-      const double* av = W.a_val + (size_t)r * Wc;
-      for (int e = sub; e < len; e += 8) acc += av[e] * z[ac[e]];
-    }
-    acc = sum8(acc);
-    if (sub == 0 && r < n) {
-      const double x = (r == unit ? 1.0 : 0.0) - acc;
-      rv[r] = x;
-      nl += x * x;
-    }
+// r = e_unit - A z in FP64; returns ||r||_2.  z is staged in LDS when the
+// solve region can hold it, otherwise gathered from global memory.
+__device__ inline double wg_resid64(const Walker& W, const double* z, int unit, double* rv, Smem& S,
+                                    size_t stage_bytes) {
+  const int n = W.n;
+  double sq;
+  if ((size_t)n * 8 <= stage_bytes) {
+    double* zs = (double*)S.A;
+    for (int r = threadIdx.x; r < n; r += NT) zs[r] = z[r];
+    __syncthreads();
+    sq = wg_rows_apply<double, double, double, double>(W, W.a_val, zs, rv, unit, true);
+  } else {
+    sq = wg_rows_apply<double, double, double, double>(W, W.a_val, z, rv, unit, true);
   }
   __syncthreads();
-  return sqrt(wg_sum(nl, S.red));
+  return sqrt(wg_sum(sq, S.red));
 }
 
 // h[i] = sum_r w[r] V_i[r] for i < cnt (FP64 reduction), written to out[] (LDS).
@@ -351,9 +456,12 @@ __device__ inline SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, 
     const KT* vj = V + (size_t)j * n;
     wg_precond<KT>(W, m, P.m_max, (j == 0 && unit_rhs) ? nullptr : vj, unit, xs, S);
     KT* xp = Xp + (size_t)j * n;
+    PhaseClock pc;
+    pc.start();
     for (int r = threadIdx.x; r < n; r += NT) xp[r] = xs[r];
     wg_spmv<KT>(W, aval, xs, w);
     __syncthreads();
+    pc.stop(S, PH_SPMV);
     // effective stability: ||v_j - A M v_j||
     double nl = 0.0;
     for (int r = threadIdx.x; r < n; r += NT) {
@@ -409,6 +517,7 @@ __device__ inline SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, 
       S.ic[3] = (den == 0.0) ? 1 : 0;
     }
     __syncthreads();
+    pc.stop(S, PH_ORTHO);
     res = S.sc[0];
     conv = S.ic[2];
     const int broke = S.ic[3];
@@ -416,6 +525,8 @@ __device__ inline SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, 
     if (conv) break;
   }
   // y = R^{-1} g, z (+)= scale * sum y_i Xp_i
+  PhaseClock pz;
+  pz.start();
   if (threadIdx.x == 0) {
     for (int i = k - 1; i >= 0; --i) {
       double s = S.gg[i];
@@ -431,6 +542,7 @@ __device__ inline SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, 
     z[r] = acc;
   }
   __syncthreads();
+  pz.stop(S, PH_SOLUTION);
   SolveOut o;
   o.iters = k;
   o.conv = conv;

@@ -99,25 +99,105 @@ __device__ inline int ilutp_row_cap_extra(const Walker& W, const DevParams& P, S
   return (int)ceil(tot / (2.0 * W.n));
 }
 
+// Fetch the diagonal, length and (when it fits) the entries of U row k for
+// every candidate that has not been fetched yet, into the LDS staging area.
+// One batch of independent loads instead of one dependent load per candidate.
+struct IluCand {
+  short* pos;    // candidate position k (CAND_DONE once eliminated)
+  double* diag;  // u_kk
+  short* off;    // staging offset; -1 not fetched; -2 fetched but read from global
+  short* len;    // off-diagonal length of U row k
+  short* scol;   // staged columns (labels)
+  double* sval;  // staged values
+};
+
+constexpr int ST_UNFETCHED = -1;
+constexpr int CAND_DONE = 32767;
+constexpr int ST_GLOBAL = -2;
+constexpr int STAGE_UNR = 16;
+
+__device__ inline void ilu_fetch_pending(const Walker& W, IluCand& C, int ncand, int& stoff) {
+  const int lane = lane_id();
+  const int F = W.F;
+  for (int s0 = 0; s0 < ncand; s0 += 64) {
+    const int s = s0 + lane;
+    bool need = false;
+    int k = 0, len = 0;
+    if (s < ncand && C.off[s] == ST_UNFETCHED) {
+      need = true;
+      k = C.pos[s];
+      C.diag[s] = W.u_diag[k];
+      len = W.u_len[k];
+      C.len[s] = (short)len;
+    }
+    // exclusive prefix sum of the lengths of needed slots
+    int pre = need ? len : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(pre, o, 64);
+      if (lane >= o) pre += t;
+    }
+    const int total = __shfl(pre, 63, 64);
+    pre -= need ? len : 0;
+    int off = ST_GLOBAL;
+    if (need && stoff + pre + len <= SCAP) off = stoff + pre;
+    if (need) C.off[s] = (short)off;
+    const bool stage = need && off >= 0;
+    // copy the rows: each lane its own row, STAGE_UNR entries per pass
+    for (int base = 0;; base += STAGE_UNR) {
+      const bool more = stage && base < len;
+      if (!__ballot(more)) break;
+      int cc[STAGE_UNR];
+      double vv[STAGE_UNR];
+#pragma unroll
+      for (int t = 0; t < STAGE_UNR; ++t) {
+        const int e = base + t;
+        if (more && e < len) {
+          cc[t] = W.u_col[(size_t)k * F + e];
+          vv[t] = W.u_val[(size_t)k * F + e];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < STAGE_UNR; ++t) {
+        const int e = base + t;
+        if (more && e < len) {
+          C.scol[off + e] = (short)cc[t];
+          C.sval[off + e] = vv[t];
+        }
+      }
+    }
+    if (stoff + total <= SCAP) stoff += total;
+    else stoff = SCAP;  // later fetches read from global
+  }
+}
+
 __device__ inline int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
   const int n = W.n;
   const int F = W.F;
   const int pfill = ilutp_row_cap_extra(W, P, S);
   char* base = S.A;
   double* wv = (double*)base;               base += align_up((size_t)n * 8, 16);
-  unsigned char* present = (unsigned char*)base; base += align_up((size_t)n, 16);
+  unsigned* pbits = (unsigned*)base;        base += align_up((size_t)(n + 31) / 32 * 4, 16);
   short* pinv = (short*)base;               base += align_up((size_t)n * 2, 16);
   short* q = (short*)base;                  base += align_up((size_t)n * 2, 16);
   short* nzc = (short*)base;                base += align_up((size_t)NZMAX * 2, 16);
   short* lk = (short*)base;                 base += align_up((size_t)LMAX * 2, 16);
-  double* lv = (double*)base;
+  double* lv = (double*)base;               base += align_up((size_t)LMAX * 8, 16);
+  const int cmax = ilu_cmax(n);
+  IluCand C;
+  C.diag = (double*)base;                   base += (size_t)cmax * 8;
+  C.pos = (short*)base;                     base += align_up((size_t)cmax * 2, 16);
+  C.off = (short*)base;                     base += align_up((size_t)cmax * 2, 16);
+  C.len = (short*)base;                     base += align_up((size_t)cmax * 2, 16);
+  C.scol = (short*)base;                    base += align_up((size_t)SCAP * 2, 16);
+  C.sval = (double*)base;
 
   for (int k = threadIdx.x; k < n; k += NT) {
     wv[k] = 0.0;
-    present[k] = 0;
     pinv[k] = (short)k;
     q[k] = (short)k;
   }
+  for (int k = threadIdx.x; k < (n + 31) / 32; k += NT) pbits[k] = 0u;
   __syncthreads();
 
   int status = WST_OK;
@@ -125,96 +205,123 @@ __device__ inline int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
     const int lane = lane_id();
     const double droptol = P.droptol, permtol = P.permtol;
     for (int i = 0; i < n && status == WST_OK; ++i) {
-      // 1. load row i
+      // 1. load row i; its entries left of the diagonal are the first candidates
       const int len = W.a_len[i];
       double nrm = 0.0;
       int nl0 = 0, nu0 = 0;
-      for (int e = lane; e < len; e += 64) {
-        const int c = W.a_col[(size_t)i * W.W + e];
-        const double v = W.a_val[(size_t)i * W.W + e];
-        wv[c] = v;
-        present[c] = 1;
-        nzc[e] = (short)c;
-        nrm += v * v;
-        const int k = pinv[c];
-        nl0 += (k < i);
-        nu0 += (k > i);
+      int ncand = 0;
+      for (int e0 = 0; e0 < len; e0 += 64) {
+        const int e = e0 + lane;
+        bool cand = false;
+        int k = 0;
+        if (e < len) {
+          const int c = W.a_col[(size_t)i * W.W + e];
+          const double v = W.a_val[(size_t)i * W.W + e];
+          wv[c] = v;
+          atomicOr(&pbits[c >> 5], 1u << (c & 31));
+          nzc[e] = (short)c;
+          nrm += v * v;
+          k = pinv[c];
+          nl0 += (k < i);
+          nu0 += (k > i);
+          cand = k < i;
+        }
+        const unsigned long long mask = __ballot(cand);
+        const int before = __popcll(mask & ((1ull << lane) - 1ull));
+        if (cand && ncand + before < cmax) {
+          C.pos[ncand + before] = (short)k;
+          C.off[ncand + before] = ST_UNFETCHED;
+        }
+        ncand += __popcll(mask);
       }
+      if (ncand > cmax) { status = WST_CAPACITY; break; }
       nrm = wave_sum(nrm);
       nl0 = wave_sumi(nl0);
       nu0 = wave_sumi(nu0);
       const double tau = droptol * sqrt(nrm);
       int nz = len;
       int lcount = 0;
-      int kcur = -1;
+      int stoff = 0;
       // 2. eliminate in increasing position order
       while (true) {
-        int best = 0x7fffffff;
-        for (int e = lane; e < nz; e += 64) {
-          const int k = pinv[nzc[e]];
-          if (k > kcur && k < i && k < best) best = k;
+        int best = CAND_DONE, bslot = -1;
+        for (int s = lane; s < ncand; s += 64) {
+          const int p = C.pos[s];
+          if (p < best) { best = p; bslot = s; }
         }
-        best = wave_mini(best);
-        if (best == 0x7fffffff) break;
-        kcur = best;
+        {
+          // positions are distinct, so exactly one lane holds the minimum
+          const int bmin = wave_mini(best);
+          if (bmin == CAND_DONE) break;
+          const unsigned long long who = __ballot(best == bmin);
+          bslot = readlane_i(bslot, __ffsll((long long)who) - 1);
+          best = bmin;
+        }
+        if (C.off[bslot] == ST_UNFETCHED) ilu_fetch_pending(W, C, ncand, stoff);
         const int c = q[best];
-        const double lik = wv[c] / W.u_diag[best];
+        const double lik = wv[c] / C.diag[bslot];
+        if (lane == 0) C.pos[bslot] = (short)CAND_DONE;
         if (fabs(lik) < tau) continue;
-        if (lcount < LMAX) {
-          if (lane == 0) { lk[lcount] = (short)best; lv[lcount] = lik; }
-        } else {
-          status = WST_CAPACITY;
-          break;
-        }
+        if (lcount >= LMAX) { status = WST_CAPACITY; break; }
+        if (lane == 0) { lk[lcount] = (short)best; lv[lcount] = lik; }
         ++lcount;
-        const int ul = W.u_len[best];
-        const int* ucol = W.u_col + (size_t)best * F;
-        const double* uval = W.u_val + (size_t)best * F;
+        const int ul = C.len[bslot];
+        const int uoff = C.off[bslot];
         for (int e0 = 0; e0 < ul; e0 += 64) {
           const int e = e0 + lane;
-          bool isnew = false;
-          int c2 = 0;
+          bool isnew = false, newcand = false;
+          int c2 = 0, k2 = 0;
           double v2 = 0.0;
           if (e < ul) {
-            c2 = ucol[e];
-            v2 = uval[e];
-            if (present[c2]) {
+            if (uoff >= 0) {
+              c2 = C.scol[uoff + e];
+              v2 = C.sval[uoff + e];
+            } else {
+              c2 = W.u_col[(size_t)best * F + e];
+              v2 = W.u_val[(size_t)best * F + e];
+            }
+            const unsigned bit = 1u << (c2 & 31);
+            const unsigned old = atomicOr(&pbits[c2 >> 5], bit);
+            if (old & bit) {
               wv[c2] -= lik * v2;
             } else {
+              wv[c2] = -lik * v2;
               isnew = true;
+              k2 = pinv[c2];
+              newcand = k2 < i;
             }
           }
           unsigned long long mask = __ballot(isnew);
-          const int before = __popcll(mask & ((1ull << lane) - 1ull));
-          if (isnew) {
-            const int o = nz + before;
-            wv[c2] = -lik * v2;
-            present[c2] = 1;
-            if (o < NZMAX) nzc[o] = (short)c2;
-          }
+          int before = __popcll(mask & ((1ull << lane) - 1ull));
+          if (isnew && nz + before < NZMAX) nzc[nz + before] = (short)c2;
           nz += __popcll(mask);
+          mask = __ballot(newcand);
+          before = __popcll(mask & ((1ull << lane) - 1ull));
+          if (newcand && ncand + before < cmax) {
+            C.pos[ncand + before] = (short)k2;
+            C.off[ncand + before] = ST_UNFETCHED;
+          }
+          ncand += __popcll(mask);
         }
-        if (nz > NZMAX) { status = WST_CAPACITY; break; }
+        if (nz > NZMAX || ncand > cmax) { status = WST_CAPACITY; break; }
       }
       if (status != WST_OK) break;
 
       // 3./4. U part: threshold drop (never the current diagonal column), fill limit
       const int cd = q[i];
+      const bool cd_present = (pbits[cd >> 5] >> (cd & 31)) & 1u;
       const int ucap = nu0 + pfill;
       const int lcap = nl0 + pfill;
-      // count off-diagonal candidates
       int ucnt = 0;
       for (int e = lane; e < nz; e += 64) {
         const int c = nzc[e];
         if (c != cd && pinv[c] >= i && fabs(wv[c]) >= tau) ++ucnt;
       }
       ucnt = wave_sumi(ucnt);
-      // rank threshold: an off-diagonal candidate is kept when fewer than ucap
-      // candidates precede it in (|v| desc, position asc) order
       double vmax = -1.0;
       int cmax_pos = 0x7fffffff;
-      const double vd = present[cd] ? wv[cd] : 0.0;
-      if (present[cd]) { vmax = fabs(vd); cmax_pos = i; }
+      const double vd = cd_present ? wv[cd] : 0.0;
+      if (cd_present) { vmax = fabs(vd); cmax_pos = i; }
       int uwrite = 0;
       int* out_col = W.u_col + (size_t)i * F;
       double* out_val = W.u_val + (size_t)i * F;
@@ -254,7 +361,6 @@ __device__ inline int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
         }
         uwrite += __popcll(mask);
       }
-      // wave argmax of (|v| desc, position asc)
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
         const double ov = __shfl_xor(vmax, o, 64);
@@ -264,11 +370,9 @@ __device__ inline int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
       if (uwrite > F - 1) { status = WST_CAPACITY; break; }
       if (!(vmax > 0.0)) { status = WST_SINGULAR; break; }
       // 5. pivot: swap the diagonal column with the largest entry's column
-      int newdiag = cd;
       double dval = vd;
       if (permtol * vmax > fabs(vd) && cmax_pos != i) {
         const int cm = q[cmax_pos];
-        newdiag = cm;
         dval = wv[cm];
         if (lane == 0) {
           q[i] = (short)cm;
@@ -277,16 +381,14 @@ __device__ inline int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
           pinv[cd] = (short)cmax_pos;
         }
         // the new diagonal leaves the off-diagonal list; the old diagonal joins it
-        // (present entries only)
         int slot = -1;
         for (int e = lane; e < uwrite; e += 64)
           if (out_col[e] == cm) slot = e;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) slot = max(slot, __shfl_xor(slot, o, 64));
-        if (present[cd]) {
+        if (cd_present) {
           if (lane == 0) { out_col[slot] = cd; out_val[slot] = vd; }
         } else {
-          // move the last entry into the hole
           if (lane == 0) {
             out_col[slot] = out_col[uwrite - 1];
             out_val[slot] = out_val[uwrite - 1];
@@ -330,12 +432,11 @@ __device__ inline int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
         W.l_len[i] = lwrite;
       }
       // 6. clear the work row
-      for (int e = lane; e < nz && e < NZMAX; e += 64) {
+      for (int e = lane; e < nz; e += 64) {
         const int c = nzc[e];
         wv[c] = 0.0;
-        present[c] = 0;
+        pbits[c >> 5] = 0u;
       }
-      (void)newdiag;
       __threadfence_block();
     }
   }

@@ -12,27 +12,53 @@ namespace vmc {
 // (eq. (matrixUpdateU)), written to the walker's pending buffers.  Returns
 // WST_*; the row position and the lengths come back through S.ic[4..6].
 __device__ inline int wg_prepare(const Walker& W, Smem& S, int p, const double* rnew) {
+  PhaseClock pc;
+  pc.start();
   const int i = W.rpos[p];
+  // LDS staging of the old and the new row (the solve region is free here)
+  int* oc = (int*)S.A;
+  double* ov = (double*)(S.A + align_up((size_t)W.W * 4, 16));
+  int* nc = (int*)(S.A + align_up((size_t)W.W * 4, 16) + (size_t)W.W * 8);
+  double* nv = (double*)((char*)nc + align_up((size_t)W.W * 4, 16));
+  const int lo = W.a_len[i];
+  for (int e = threadIdx.x; e < lo; e += NT) {
+    oc[e] = W.a_col[(size_t)i * W.W + e];
+    ov[e] = W.a_val[(size_t)i * W.W + e];
+  }
   if (wave_id() == 0) {
     const int lane = lane_id();
     int st = WST_OK;
-    const int cnt = wave_row(W, rnew[0], rnew[1], rnew[2], W.cpos, W.new_col, W.new_val, nullptr, W.W);
+    const int cnt = wave_row(W, rnew[0], rnew[1], rnew[2], W.cpos, nc, nv, nullptr, W.W);
     int ul = 0;
     if (cnt > W.W) {
       st = WST_CAPACITY;
     } else {
-      __threadfence_block();
-      const int lo = W.a_len[i];
-      const int* oc = W.a_col + (size_t)i * W.W;
-      const double* ov = W.a_val + (size_t)i * W.W;
-      for (int e = lane; e < cnt; e += 64) {
-        const int c = W.new_col[e];
-        double vo = 0.0;
-        for (int f = 0; f < lo; ++f)
-          if (oc[f] == c) { vo = ov[f]; break; }
-        W.pu_col[e] = c;
-        W.pu_val[e] = W.new_val[e] - vo;
-      }
+      S.ic[10] = 0;
+    }
+    if (lane == 0) {
+      S.ic[4] = i;
+      S.ic[5] = cnt;
+      S.ic[7] = st;
+    }
+  }
+  __syncthreads();
+  const int cnt = S.ic[5];
+  int st = S.ic[7];
+  int ul = 0;
+  if (st == WST_OK) {
+    // u = new row - old row over the union of the two patterns (eq. (matrixUpdateU))
+    for (int e = threadIdx.x; e < cnt; e += NT) {
+      const int c = nc[e];
+      double vo = 0.0;
+      for (int f = 0; f < lo; ++f)
+        if (oc[f] == c) { vo = ov[f]; break; }
+      W.pu_col[e] = c;
+      W.pu_val[e] = nv[e] - vo;
+      W.new_col[e] = c;
+      W.new_val[e] = nv[e];
+    }
+    if (wave_id() == 0) {
+      const int lane = lane_id();
       ul = cnt;
       for (int e0 = 0; e0 < lo; e0 += 64) {
         const int e = e0 + lane;
@@ -42,9 +68,9 @@ __device__ inline int wg_prepare(const Walker& W, Smem& S, int p, const double* 
           c = oc[e];
           miss = true;
           for (int f = 0; f < cnt; ++f)
-            if (W.new_col[f] == c) { miss = false; break; }
+            if (nc[f] == c) { miss = false; break; }
         }
-        unsigned long long mask = __ballot(miss);
+        const unsigned long long mask = __ballot(miss);
         const int before = __popcll(mask & ((1ull << lane) - 1ull));
         if (miss) {
           W.pu_col[ul + before] = c;
@@ -52,17 +78,12 @@ __device__ inline int wg_prepare(const Walker& W, Smem& S, int p, const double* 
         }
         ul += __popcll(mask);
       }
-      __threadfence_block();
-    }
-    if (lane == 0) {
-      S.ic[4] = i;
-      S.ic[5] = cnt;
-      S.ic[6] = ul;
-      S.ic[7] = st;
+      if (lane == 0) S.ic[6] = ul;
     }
   }
+  __threadfence_block();
   __syncthreads();
-  const int st = S.ic[7];
+  pc.stop(S, PH_PREPARE);
   return st;
 }
 
@@ -102,8 +123,12 @@ __device__ inline StepSolve wg_solve(const Walker& W, int m, const DevParams& P,
     o.conv = 0;
     int pass = 0;
     while (true) {
-      const double rn = wg_resid64(W, W.zvec, i, W.rvec, S);
+      PhaseClock pc;
+      pc.start();
+      const size_t stage = align_up((size_t)W.n, 4) * 4 + (size_t)BLK * BLK * 4;
+      const double rn = wg_resid64(W, W.zvec, i, W.rvec, S, stage);
       o.ratio = wg_ratio(W, ulen, W.zvec, S);
+      pc.stop(S, PH_RESID);
       o.res = rn;
       if (rn <= P.refine_tol * fmin(1.0, fabs(o.ratio))) { o.conv = 1; break; }
       if (pass >= P.refine_maxit || !(rn > 0.0)) break;
@@ -121,10 +146,15 @@ __device__ inline StepSolve wg_solve(const Walker& W, int m, const DevParams& P,
 // Geometric reorder, rebuild of A in the new order, ILUTP (Section 3.1/3.2).
 template <int PREC>
 __device__ inline int wg_reorder_refactor(const Walker& W, const DevParams& P, Smem& S) {
+  PhaseClock pc;
+  pc.start();
   wg_reorder(W, S);
   int st = wg_build_all_rows(W, S);
+  pc.stop(S, PH_REORDER);
   if (st != WST_OK) return st;
-  return wg_ilutp(W, P, S);
+  st = wg_ilutp(W, P, S);
+  pc.stop(S, PH_REFACTOR);
+  return st;
 }
 
 // Append the rank-one factor of an accepted move (eq. (mkp1)): zhat = z/ratio,
@@ -208,6 +238,7 @@ __device__ inline void wg_det_ratio(const Walker& W, WalkerState* ws, const DevP
       ws->st_solves += 1;
       ws->st_inner += o.inner;
       ws->st_refine += o.passes;
+      ws->st_msum += (long long)m * o.inner;
     }
     if (trig) {
       flags |= VMC_FLAG_REORDERED;
@@ -270,6 +301,8 @@ __device__ inline void wg_accept(const Walker& W, WalkerState* ws, const DevPara
   const double ratio = ws->pend_ratio;
   int flags = ws->pend_flags;
   int st = WST_OK;
+  PhaseClock pc;
+  pc.start();
   if (accept) {
     flags |= VMC_FLAG_ACCEPTED;
     for (int e = threadIdx.x; e < newlen; e += NT) {
@@ -288,7 +321,9 @@ __device__ inline void wg_accept(const Walker& W, WalkerState* ws, const DevPara
     __syncthreads();
     const int m = ws->m;
     if (m + 1 >= P.m_max) {
+      pc.stop(S, PH_ACCEPT);
       st = wg_ilutp(W, P, S);
+      pc.stop(S, PH_REFACTOR);
       flags |= VMC_FLAG_REFACTORED;
       if (threadIdx.x == 0) {
         ws->m = 0;
@@ -299,6 +334,7 @@ __device__ inline void wg_accept(const Walker& W, WalkerState* ws, const DevPara
       if (threadIdx.x == 0) ws->m = m + 1;
     }
   }
+  pc.stop(S, PH_ACCEPT);
   __syncthreads();
   if (threadIdx.x == 0) {
     if (rec) {

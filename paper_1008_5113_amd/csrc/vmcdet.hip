@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -35,6 +36,7 @@ __global__ void __launch_bounds__(NT) k_setup(const Walker* __restrict__ walkers
   const int w = list ? list[blockIdx.x] : (int)blockIdx.x;
   const Walker& W = walkers[w];
   Smem S = setup_smem(smem, W, P, PREC == VMC_PREC_FP64 ? 8 : 4);
+  S.ph = states[w].ph;
   if (threadIdx.x < 32) S.ic[threadIdx.x] = 0;
   __syncthreads();
   int st = WST_OK;
@@ -55,7 +57,7 @@ __global__ void __launch_bounds__(NT) k_setup(const Walker* __restrict__ walkers
 }
 
 template <int PREC>
-__global__ void __launch_bounds__(NT) k_ratio(const Walker* __restrict__ walkers, WalkerState* states,
+__global__ void __launch_bounds__(NT, 4) k_ratio(const Walker* __restrict__ walkers, WalkerState* states,
                                               DevParams P, const int* list, const int* particles,
                                               const double* newpos, vmc_step_record* out) {
   extern __shared__ __align__(16) char smem[];
@@ -63,6 +65,7 @@ __global__ void __launch_bounds__(NT) k_ratio(const Walker* __restrict__ walkers
   const Walker& W = walkers[w];
   WalkerState* ws = states + w;
   Smem S = setup_smem(smem, W, P, PREC == VMC_PREC_FP64 ? 8 : 4);
+  S.ph = states[w].ph;
   if (threadIdx.x < 32) S.ic[threadIdx.x] = 0;
   __syncthreads();
   if (ws->status != WST_OK) {
@@ -113,6 +116,7 @@ __global__ void __launch_bounds__(NT) k_accept(const Walker* __restrict__ walker
   const Walker& W = walkers[w];
   WalkerState* ws = states + w;
   Smem S = setup_smem(smem, W, P, PREC == VMC_PREC_FP64 ? 8 : 4);
+  S.ph = states[w].ph;
   if (threadIdx.x < 32) S.ic[threadIdx.x] = 0;
   __syncthreads();
   if (!ws->pend_valid) {
@@ -134,15 +138,18 @@ __global__ void __launch_bounds__(NT) k_accept(const Walker* __restrict__ walker
 
 // Persistent fused path: `steps` Metropolis steps of one walker per workgroup.
 template <int PREC>
-__global__ void __launch_bounds__(NT) k_run(const Walker* __restrict__ walkers, WalkerState* states,
+__global__ void __launch_bounds__(NT, 4) k_run(const Walker* __restrict__ walkers, WalkerState* states,
                                             DevParams P, int steps, vmc_step_record* log, long long log_cap) {
   extern __shared__ __align__(16) char smem[];
   const int w = blockIdx.x;
   const Walker& W = walkers[w];
   WalkerState* ws = states + w;
   Smem S = setup_smem(smem, W, P, PREC == VMC_PREC_FP64 ? 8 : 4);
+  S.ph = states[w].ph;
   if (threadIdx.x < 32) S.ic[threadIdx.x] = 0;
   __syncthreads();
+  PhaseClock pstep;
+  pstep.start();
   for (int s = 0; s < steps; ++s) {
     if (ws->status != WST_OK) break;
     const long long g = ws->g;
@@ -157,6 +164,45 @@ __global__ void __launch_bounds__(NT) k_run(const Walker* __restrict__ walkers, 
     const long long slot = (long long)w * steps + s;
     vmc_step_record* rec = (log && slot < log_cap) ? log + slot : nullptr;
     wg_accept<PREC>(W, ws, P, S, acc, w, rec);
+  }
+  pstep.stop(S, PH_STEP);
+}
+
+// Diagnostic: one phase of the solve, repeated `reps` times per walker on the
+// walker's current matrix and factors (no state change except ILUTP).
+template <int PREC>
+__global__ void __launch_bounds__(NT, 4) k_phase(const Walker* __restrict__ walkers, WalkerState* states,
+                                                 DevParams P, int phase, int reps) {
+  extern __shared__ __align__(16) char smem[];
+  using KT = typename std::conditional<PREC == VMC_PREC_FP64, double, float>::type;
+  const int w = blockIdx.x;
+  const Walker& W = walkers[w];
+  Smem S = setup_smem(smem, W, P, sizeof(KT));
+  if (threadIdx.x < 32) S.ic[threadIdx.x] = 0;
+  const int n = W.n;
+  KT* xs = (KT*)S.A;
+  KT* D = xs + align_up((size_t)n, 4);
+  KT* st = (KT*)S.stmp;
+  for (int e = threadIdx.x; e < BLK * BLK; e += NT) D[e] = (KT)0;
+  for (int r = threadIdx.x; r < n; r += NT) xs[r] = (KT)(1.0 / (1.0 + r));
+  __syncthreads();
+  const int m = states[w].m;
+  for (int it = 0; it < reps; ++it) {
+    switch (phase) {
+      case 0: wg_spmv<KT>(W, Fac<KT>::aval(W), xs, (KT*)W.wv); break;
+      case 1: wg_lsolve<KT>(W, Fac<KT>::lval(W), nullptr, it % n, xs, D, st); break;
+      case 2: wg_usolve<KT>(W, Fac<KT>::usval(W), Fac<KT>::dinv(W), xs, D, st); break;
+      case 3: wg_updates<KT>(W, m, P.m_max, xs, S); break;
+      case 4: {
+        const size_t stage = align_up((size_t)n, 4) * 4 + (size_t)BLK * BLK * 4;
+        (void)wg_resid64(W, W.zvec, it % n, W.rvec, S, stage);
+        for (int e = threadIdx.x; e < BLK * BLK; e += NT) D[e] = (KT)0;
+        break;
+      }
+      case 5: (void)wg_ilutp(W, P, S); break;
+      default: break;
+    }
+    __syncthreads();
   }
 }
 
@@ -327,6 +373,7 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
     int Wc = p->row_cap > 0 ? p->row_cap
                             : lattice_bound(in.cutoff + in.site_margin + 0.8660254037844387 * in.a, in.a);
     Wc = std::min(Wc, n);
+    Wc = (Wc + 3) / 4 * 4;  // 16-byte aligned rows for vector loads
     W.W = Wc;
     W.F = std::min(n, Wc + (Wc + 1) / 2 + 2);
     W.UC = 2 * Wc;
@@ -584,6 +631,20 @@ vmc_status vmc_run_sweeps(void* ctx, int32_t sweeps, vmc_step_record* dev_log, i
   return vmc_run_steps(ctx, (int32_t)steps, dev_log, log_cap);
 }
 
+vmc_status vmc_phase_bench(void* ctx, int32_t phase, int32_t reps) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || phase < 0 || phase > 5 || reps < 0) return VMC_EINVAL;
+  if (c->dp.precision == VMC_PREC_FP64) {
+    (void)hipFuncSetAttribute((const void*)k_phase<VMC_PREC_FP64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
+    hipLaunchKernelGGL(k_phase<VMC_PREC_FP64>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, phase, reps);
+  } else {
+    (void)hipFuncSetAttribute((const void*)k_phase<VMC_PREC_MIXED>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
+    hipLaunchKernelGGL(k_phase<VMC_PREC_MIXED>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, phase, reps);
+  }
+  HIPCHK(c, hipGetLastError());
+  return VMC_OK;
+}
+
 vmc_status vmc_sync(void* ctx) {
   Ctx* c = (Ctx*)ctx;
   if (!c) return VMC_EINVAL;
@@ -654,6 +715,8 @@ vmc_status vmc_get_stats(void* ctx, vmc_stats* out) {
     o.nonconverged = s.st_nonconv;
     o.inner_solves = s.st_inner;
     o.refine_passes = s.st_refine;
+    o.update_sum = s.st_msum;
+    for (int k = 0; k < PH_COUNT && k < 12; ++k) o.phase_ticks[k] = (int64_t)s.ph[k];
     o.max_N = s.st_maxN;
     o.sum_N = s.st_sumN;
     o.status = (s.status & WST_CAPACITY) ? VMC_ECAPACITY : (s.status & WST_SINGULAR) ? VMC_ESINGULAR : VMC_OK;

@@ -14,7 +14,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libvmcdet.so")
+LIB_PATH = os.environ.get("VMCDET_LIB") or os.path.join(_HERE, "libvmcdet.so")
 
 VMC_OK = 0
 VMC_EINVAL = -1
@@ -35,11 +35,16 @@ FLAG_CONVERGED = 8
 FLAG_SINGULAR = 16
 FLAG_CAPACITY = 32
 
+PHASE_NAMES = ["prepare", "lsolve", "usolve", "updates", "spmv", "ortho", "solution", "resid64",
+               "accept", "refactor", "reorder", "launch"]
+WALL_CLOCK_HZ = 100e6  # device wall clock (s_memrealtime) on CDNA3/CDNA4
+
 EXPORTED = [
     "vmc_default_params", "vmc_create", "vmc_build_slater", "vmc_ilutp", "vmc_det_ratio",
     "vmc_accept", "vmc_run_steps", "vmc_run_sweeps", "vmc_sync", "vmc_get_dims",
-    "vmc_get_state", "vmc_get_stats", "vmc_last_error", "vmc_destroy",
+    "vmc_get_state", "vmc_get_stats", "vmc_last_error", "vmc_destroy", "vmc_phase_bench",
 ]
+PHASE_BENCH = {"spmv": 0, "lsolve": 1, "usolve": 2, "updates": 3, "resid64": 4, "ilutp": 5}
 
 
 class VmcParams(ctypes.Structure):
@@ -117,7 +122,9 @@ class VmcStats(ctypes.Structure):
         ("steps", ctypes.c_int64), ("accepted", ctypes.c_int64), ("solves", ctypes.c_int64),
         ("iters", ctypes.c_int64), ("reorders", ctypes.c_int64), ("refactors", ctypes.c_int64),
         ("nonconverged", ctypes.c_int64), ("inner_solves", ctypes.c_int64),
-        ("refine_passes", ctypes.c_int64), ("max_N", ctypes.c_double), ("sum_N", ctypes.c_double),
+        ("refine_passes", ctypes.c_int64), ("update_sum", ctypes.c_int64),
+        ("phase_ticks", ctypes.c_int64 * 12),
+        ("max_N", ctypes.c_double), ("sum_N", ctypes.c_double),
         ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
     ]
 
@@ -144,6 +151,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.vmc_last_error.argtypes = [P]
     lib.vmc_last_error.restype = ctypes.c_char_p
     lib.vmc_destroy.argtypes = [P]
+    lib.vmc_phase_bench.argtypes = [P, i32, i32]
     for name in EXPORTED:
         if name != "vmc_last_error":
             getattr(lib, name).restype = i32
@@ -306,6 +314,9 @@ class Context:
         arr = buf.cpu().numpy().view(STEP_RECORD_DTYPE)
         return arr.reshape(self.n_walkers, steps)
 
+    def phase_bench(self, phase: str, reps: int):
+        self._check(lib().vmc_phase_bench(self.h, PHASE_BENCH[phase], int(reps)))
+
     def sync(self):
         self._check(lib().vmc_sync(self.h))
 
@@ -336,5 +347,10 @@ class Context:
     def stats(self):
         arr = (VmcStats * self.n_walkers)()
         self._check(lib().vmc_get_stats(self.h, ctypes.cast(arr, ctypes.c_void_p)))
-        keys = [f[0] for f in VmcStats._fields_ if f[0] != "pad"]
-        return [{k: getattr(arr[i], k) for k in keys} for i in range(self.n_walkers)]
+        keys = [f[0] for f in VmcStats._fields_ if f[0] not in ("pad", "phase_ticks")]
+        out = []
+        for i in range(self.n_walkers):
+            d = {k: getattr(arr[i], k) for k in keys}
+            d["phase_ticks"] = list(arr[i].phase_ticks)
+            out.append(d)
+        return out

@@ -94,9 +94,16 @@ def test_reorder_exact_matching_configuration(vm):
     ctx.close()
 
 
-def test_ilutp_against_oracle(vm):
-    _say("case: ilutp plain_n128")
-    inst = wl.plain_n128()
+def _px_instance():
+    s = wl.make_system((8, 8, 10), sigma=0.35, kind=wl.ORB_GAUSS_PX, p_scale=0.1, p_sigma=0.5, cutoff=2.5)
+    w = [wl.Walker(0, wl.initial_positions(s.sites, s.box, 3, 0.3), 3)]
+    return wl.Instance("px_n640", [s], w, wl.Params(step=0.25))
+
+
+@pytest.mark.parametrize("which", ["plain_n128", "px_n640"])
+def test_ilutp_against_oracle(vm, which):
+    _say(f"case: ilutp {which}")
+    inst = wl.plain_n128() if which == "plain_n128" else _px_instance()
     s = inst.systems[0]
     ctx = vm.Context.from_instance(inst)
     ctx.ilutp(reorder=True)
