@@ -5,6 +5,9 @@
 
 namespace vmc {
 
+// Phase-level device functions (inlined into the fused kernels).
+#define VMC_PHASE __device__ inline
+
 // ---------------------------------------------------------------------------
 // Shared-memory layout.  Region A is a union of the phase-private buffers
 // (Krylov/triangular-solve vectors, the ILUTP work row, the reorder

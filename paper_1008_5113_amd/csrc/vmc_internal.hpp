@@ -8,6 +8,17 @@
 
 namespace vmc {
 
+// Pointer members of the walker table point to device global memory.  The
+// device compilation pass says so explicitly (address space 1), so loads
+// through them become global_load instructions, which only wait on the vector
+// memory counter, instead of FLAT loads, which also hold the LDS counter and
+// would make every LDS wait and barrier drain the prefetched loads.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GAS __attribute__((address_space(1)))
+#else
+#define GAS
+#endif
+
 constexpr int NT = 512;        // threads per walker workgroup
 constexpr int NWAVE = NT / 64;
 constexpr int BLK = 64;        // rows per triangular-solve block (one lane per row)
@@ -64,60 +75,67 @@ struct Walker {
   unsigned long long seed;
 
   // system (by site id) and positions (by particle id)
-  const double* sites;        // n*3
-  const double* sigma;        // n
-  double* pos;                // n*3
+  const double GAS* sites;        // n*3
+  const double GAS* sigma;        // n
+  double GAS* pos;                // n*3
 
   // orderings
-  int* rowperm;               // row position -> particle
-  int* rpos;                  // particle -> row position
-  int* cpos;                  // site -> column position
-  int* colsite;               // column position -> site
-  int* reo_row;               // last geometric reorder (particle per position)
-  int* reo_col;               // last geometric reorder (site per position)
+  int GAS* rowperm;               // row position -> particle
+  int GAS* rpos;                  // particle -> row position
+  int GAS* cpos;                  // site -> column position
+  int GAS* colsite;               // column position -> site
+  int GAS* reo_row;               // last geometric reorder (particle per position)
+  int GAS* reo_col;               // last geometric reorder (site per position)
 
   // Slater matrix
-  int* a_len;
-  int* a_col;
-  double* a_val;
-  float* a_val32;
+  int GAS* a_len;
+  int GAS* a_col;
+  double GAS* a_val;
+  float GAS* a_val32;
 
   // ILU factors (column positions); U stored off-diagonal, scaled copies for the solve
-  int* l_len;
-  int* l_col;
-  double* l_val;
-  float* l_val32;
-  int* u_len;
-  int* u_col;
-  double* u_val;              // unscaled off-diagonal U
-  double* u_diag;
-  double* us_val;             // D^{-1} U off-diagonal (FP64 solve)
-  float* us_val32;            // D^{-1} U off-diagonal (FP32 solve)
-  double* u_dinv;
-  float* u_dinv32;
-  int* ilu_q;                 // last ILUTP column permutation (labels before it)
+  int GAS* l_len;
+  int GAS* l_col;
+  double GAS* l_val;
+  int GAS* u_len;
+  int GAS* u_col;
+  double GAS* u_val;              // unscaled off-diagonal U
+  double GAS* u_diag;
+  double GAS* u_dinv;
+  float GAS* u_dinv32;
+  // compact CSR copies for the triangular solves, rebuilt after every
+  // factorisation; column word = (row & 63) << 16 | column position
+  int GAS* lp;                    // n+1
+  int GAS* lc;
+  double GAS* lv64;
+  float GAS* lv32;
+  int GAS* up;                    // n+1
+  int GAS* uc;
+  double GAS* uv64;               // D^{-1} U off-diagonal
+  float GAS* uv32;
+  int GAS* ilu_q;                 // last ILUTP column permutation (labels before it)
 
   // rank-one updates M <- (I - zhat u^T) M, oldest first
-  double* Z64;                // m_max * n
-  float* Z32;
-  int* up_len;                // m_max
-  int* up_col;                // m_max * UC
-  double* up_val;
-  float* up_val32;
-  double* T;                  // m_max * m_max: T[s*m_max+t] = u_s^T zhat_t (t < s)
+  double GAS* Z64;                // m_max * n
+  float GAS* Z32;
+  int GAS* up_len;                // m_max
+  int GAS* up_col;                // m_max * UC
+  double GAS* up_val;
+  float GAS* up_val32;
+  double GAS* T;                  // m_max * m_max: T[s*m_max+t] = u_s^T zhat_t (t < s)
 
   // Krylov workspace (typed by the solve precision)
-  void* V;                    // (maxit+1) * n
-  void* Xp;                   // maxit * n : preconditioned basis vectors
-  void* wv;                   // n
-  double* zvec;               // n : solution z (FP64 accumulation)
-  double* rvec;               // n : FP64 residual (mixed)
+  void GAS* V;                    // (maxit+1) * n
+  void GAS* Xp;                   // maxit * n : preconditioned basis vectors
+  void GAS* wv;                   // n
+  double GAS* zvec;               // n : solution z (FP64 accumulation)
+  double GAS* rvec;               // n : FP64 residual (mixed)
 
   // pending move
-  int* new_col;               // W
-  double* new_val;            // W
-  int* pu_col;                // UC
-  double* pu_val;             // UC
+  int GAS* new_col;               // W
+  double GAS* new_val;            // W
+  int GAS* pu_col;                // UC
+  double GAS* pu_val;             // UC
 };
 
 // Mutable per-walker scalars, kept apart from the (read-mostly) pointer table.

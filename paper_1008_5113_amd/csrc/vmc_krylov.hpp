@@ -8,47 +8,22 @@ namespace vmc {
 
 template <typename KT> struct Fac;
 template <> struct Fac<double> {
-  __device__ static const double* lval(const Walker& W) { return W.l_val; }
-  __device__ static const double* usval(const Walker& W) { return W.us_val; }
+  __device__ static const double* lval(const Walker& W) { return W.lv64; }
+  __device__ static const double* usval(const Walker& W) { return W.uv64; }
   __device__ static const double* dinv(const Walker& W) { return W.u_dinv; }
   __device__ static const double* aval(const Walker& W) { return W.a_val; }
   __device__ static const double* Z(const Walker& W) { return W.Z64; }
   __device__ static const double* upval(const Walker& W) { return W.up_val; }
 };
 template <> struct Fac<float> {
-  __device__ static const float* lval(const Walker& W) { return W.l_val32; }
-  __device__ static const float* usval(const Walker& W) { return W.us_val32; }
+  __device__ static const float* lval(const Walker& W) { return W.lv32; }
+  __device__ static const float* usval(const Walker& W) { return W.uv32; }
   __device__ static const float* dinv(const Walker& W) { return W.u_dinv32; }
   __device__ static const float* aval(const Walker& W) { return W.a_val32; }
   __device__ static const float* Z(const Walker& W) { return W.Z32; }
   __device__ static const float* upval(const Walker& W) { return W.up_val32; }
 };
 
-
-constexpr int PF = 4;  // entries per thread held in registers per block (8 threads per row)
-
-// One 64-row block of a triangular factor, as seen by one of the 8 threads of a row.
-template <typename KT>
-struct RowChunk {
-  int len;
-  int col[PF];
-  KT val[PF];
-  KT aux;  // right-hand side (L) or inverse diagonal (U) of the row
-};
-
-template <typename KT>
-__device__ inline void load_chunk(RowChunk<KT>& ch, int r, int n, int len, const int* cols,
-                                  const KT* vals, int F, int sub) {
-  ch.len = (r >= 0 && r < n) ? len : 0;
-#pragma unroll
-  for (int t = 0; t < PF; ++t) {
-    const int e = sub + 8 * t;
-    if (e < ch.len) {
-      ch.col[t] = cols[(size_t)r * F + e];
-      ch.val[t] = vals[(size_t)r * F + e];
-    }
-  }
-}
 
 // In-block substitution by wave 0: lane r holds the block right-hand side of
 // row r; D (LDS, column-major 64x64) holds the in-block coefficients.  Step k
@@ -86,48 +61,70 @@ __device__ inline KT block_chain(KT a, const KT* D) {
   return a;
 }
 
-// Triangular solve by 64-row blocks.  FORWARD: L x = b with unit lower L, b =
-// rhs (global) or e_unit when rhs == nullptr.  Backward: U x = y in place on
-// xs, with U stored as D^{-1}U (unit upper, off-diagonal) and D^{-1}.
-// 8 threads per row gather the contributions of columns in already-solved
-// blocks from xs (LDS) and scatter in-block coefficients into D; wave 0 then
-// runs the in-block chain.  Row data is loaded two blocks ahead of use and
-// row lengths three blocks ahead, so the loads of later blocks are in flight
-// while the current block's chain runs.
+constexpr int PF = 4;          // entries per thread per row (8 threads per row)
+constexpr int COLMASK = 0xFFFF;
+
+__device__ inline bool is_far(bool forward, int c, int r0) {
+  return forward ? (c < r0) : (c >= r0 + BLK);
+}
+
+// Triangular solve by 64-row blocks on the compact CSR factors.  8 threads per row hold up to PF
+// entries each in registers; row data is loaded two blocks ahead of use and
+// the row pointers three blocks ahead.
+template <typename KT>
+struct RowChunk {
+  int len;
+  int col[PF];
+  KT val[PF];
+  KT aux;  // right-hand side (L) or inverse diagonal (U) of the row
+};
+
+template <typename KT>
+__device__ inline void load_row_chunk(RowChunk<KT>& ch, int r, int n, int start, int len, const int* cols,
+                                      const KT* vals, int sub) {
+  ch.len = (r >= 0 && r < n) ? len : 0;
+#pragma unroll
+  for (int t = 0; t < PF; ++t) {
+    const int e = sub + 8 * t;
+    if (e < ch.len) {
+      ch.col[t] = cols[start + e] & COLMASK;
+      ch.val[t] = vals[start + e];
+    }
+  }
+}
+
 template <typename KT, bool FORWARD>
-__device__ inline void wg_trisolve(const Walker& W, const int* lens, const int* cols, const KT* vals,
-                                   const KT* aux, int unit, KT* xs, KT* D, KT* st) {
-  const int n = W.n, F = W.F;
+VMC_PHASE void wg_trisolve_rows(const Walker& W, const int* ptr, const int* cols, const KT* vals,
+                                        const KT* aux, int unit, KT* xs, KT* D, KT* st) {
+  const int n = W.n;
   const int rr = threadIdx.x >> 3, sub = threadIdx.x & 7;
   const int nb = (n + BLK - 1) / BLK;
-  // block index sequence: 0..nb-1 forward, nb-1..0 backward
-  auto blk = [&](int t) { return FORWARD ? t : nb - 1 - t; };
-  auto row_of = [&](int t) { return (t >= 0 && t < nb) ? blk(t) * BLK + rr : -1; };
-  auto len_of = [&](int t) {
-    const int r = row_of(t);
-    return (r >= 0 && r < n) ? lens[r] : 0;
-  };
+  auto row_of = [&](int t) { return (t >= 0 && t < nb) ? (FORWARD ? t : nb - 1 - t) * BLK + rr : -1; };
   auto aux_of = [&](int r) -> KT {
     if (r < 0 || r >= n) return (KT)0;
     if (FORWARD) return aux ? aux[r] : (KT)(r == unit ? 1 : 0);
     return aux[r];
   };
+  auto ptr_of = [&](int t, int& a, int& b) {
+    const int r = row_of(t);
+    if (r >= 0 && r < n) { a = ptr[r]; b = ptr[r + 1]; } else { a = 0; b = 0; }
+  };
   RowChunk<KT> c0, c1, c2;
-  {
-    const int la = len_of(0), lb = len_of(1);
-    load_chunk(c0, row_of(0), n, la, cols, vals, F, sub);
-    c0.aux = aux_of(row_of(0));
-    load_chunk(c1, row_of(1), n, lb, cols, vals, F, sub);
-    c1.aux = aux_of(row_of(1));
-  }
-  int len2 = len_of(2);
+  int pa, pb, qa, qb;
+  ptr_of(0, pa, pb);
+  ptr_of(1, qa, qb);
+  load_row_chunk(c0, row_of(0), n, pa, pb - pa, cols, vals, sub);
+  c0.aux = aux_of(row_of(0));
+  load_row_chunk(c1, row_of(1), n, qa, qb - qa, cols, vals, sub);
+  c1.aux = aux_of(row_of(1));
+  int s2a, s2b;
+  ptr_of(2, s2a, s2b);
   for (int t = 0; t < nb; ++t) {
-    const int r0 = blk(t) * BLK;
+    const int r0 = (FORWARD ? t : nb - 1 - t) * BLK;
     const int r = r0 + rr;
-    // prefetch block t+2 and the row lengths of block t+3
-    load_chunk(c2, row_of(t + 2), n, len2, cols, vals, F, sub);
+    load_row_chunk(c2, row_of(t + 2), n, s2a, s2b - s2a, cols, vals, sub);
     c2.aux = aux_of(row_of(t + 2));
-    len2 = len_of(t + 3);
+    ptr_of(t + 3, s2a, s2b);
     KT acc = 0;
     int dpos[PF];
 #pragma unroll
@@ -136,8 +133,7 @@ __device__ inline void wg_trisolve(const Walker& W, const int* lens, const int* 
       dpos[k] = -1;
       if (e < c0.len) {
         const int c = c0.col[k];
-        const bool far = FORWARD ? (c < r0) : (c >= r0 + BLK);
-        if (far) {
+        if (is_far(FORWARD, c, r0)) {
           acc += c0.val[k] * xs[c];
         } else {
           dpos[k] = (c - r0) * BLK + rr;
@@ -145,11 +141,11 @@ __device__ inline void wg_trisolve(const Walker& W, const int* lens, const int* 
         }
       }
     }
+    const int rs = (r < n) ? ptr[r] : 0;
     for (int e = sub + 8 * PF; e < c0.len; e += 8) {
-      const int c = cols[(size_t)r * F + e];
-      const KT v = vals[(size_t)r * F + e];
-      const bool far = FORWARD ? (c < r0) : (c >= r0 + BLK);
-      if (far) acc += v * xs[c];
+      const int c = cols[rs + e] & COLMASK;
+      const KT v = vals[rs + e];
+      if (is_far(FORWARD, c, r0)) acc += v * xs[c];
       else D[(c - r0) * BLK + rr] = v;
     }
     acc = sum8(acc);
@@ -166,15 +162,12 @@ __device__ inline void wg_trisolve(const Walker& W, const int* lens, const int* 
       if (r0 + lane_id() < n) xs[r0 + lane_id()] = a;
     }
     __syncthreads();
-    // D back to zero: every thread clears the coefficients it scattered (the
-    // next block's scatter comes later in the same wave's program order)
 #pragma unroll
     for (int k = 0; k < PF; ++k)
       if (dpos[k] >= 0) D[dpos[k]] = (KT)0;
     for (int e = sub + 8 * PF; e < c0.len; e += 8) {
-      const int c = cols[(size_t)r * F + e];
-      const bool far = FORWARD ? (c < r0) : (c >= r0 + BLK);
-      if (!far) D[(c - r0) * BLK + rr] = (KT)0;
+      const int c = cols[rs + e] & COLMASK;
+      if (!is_far(FORWARD, c, r0)) D[(c - r0) * BLK + rr] = (KT)0;
     }
     c0 = c1;
     c1 = c2;
@@ -184,13 +177,13 @@ __device__ inline void wg_trisolve(const Walker& W, const int* lens, const int* 
 template <typename KT>
 __device__ inline void wg_lsolve(const Walker& W, const KT* lval, const KT* rhs, int unit, KT* xs,
                                  KT* D, KT* st) {
-  wg_trisolve<KT, true>(W, W.l_len, W.l_col, lval, rhs, unit, xs, D, st);
+  wg_trisolve_rows<KT, true>(W, W.lp, W.lc, lval, rhs, unit, xs, D, st);
 }
 
 template <typename KT>
 __device__ inline void wg_usolve(const Walker& W, const KT* usval, const KT* dinv, KT* xs, KT* D,
                                  KT* st) {
-  wg_trisolve<KT, false>(W, W.u_len, W.u_col, usval, dinv, -1, xs, D, st);
+  wg_trisolve_rows<KT, false>(W, W.up, W.uc, usval, dinv, -1, xs, D, st);
 }
 
 // x <- (I - zhat_{m-1} u_{m-1}^T) ... (I - zhat_0 u_0^T) x, in the compact form
@@ -198,7 +191,7 @@ __device__ inline void wg_usolve(const Walker& W, const KT* usval, const KT* din
 // g: 4 threads per update vector; c: one thread per update; the x update
 // reads four stored vectors per pass with every thread's rows in registers.
 template <typename KT>
-__device__ inline void wg_updates(const Walker& W, int m, int mmax, KT* xs, Smem& S) {
+VMC_PHASE void wg_updates(const Walker& W, int m, int mmax, KT* xs, Smem& S) {
   if (m <= 0) return;
   const int n = W.n;
   const KT* upv = Fac<KT>::upval(W);
@@ -375,13 +368,13 @@ __device__ inline double wg_rows_apply(const Walker& W, const VT* aval, const XT
 
 // w = A x with x in LDS.
 template <typename KT>
-__device__ inline void wg_spmv(const Walker& W, const KT* aval, const KT* xs, KT* w) {
+VMC_PHASE void wg_spmv(const Walker& W, const KT* aval, const KT* xs, KT* w) {
   wg_rows_apply<KT, KT, KT, KT>(W, aval, xs, w, -1, false);
 }
 
 // r = e_unit - A z in FP64; returns ||r||_2.  z is staged in LDS when the
 // solve region can hold it, otherwise gathered from global memory.
-__device__ inline double wg_resid64(const Walker& W, const double* z, int unit, double* rv, Smem& S,
+VMC_PHASE double wg_resid64(const Walker& W, const double* z, int unit, double* rv, Smem& S,
                                     size_t stage_bytes) {
   const int n = W.n;
   double sq;

@@ -35,7 +35,7 @@ __device__ inline int wg_build_all_rows(const Walker& W, Smem& S) {
 // Starts from the identity labelling; squared minimum-image distances; ties to
 // the first position.  Writes rowperm/rpos and colsite/cpos (reorder order)
 // and reo_row/reo_col.
-__device__ inline void wg_reorder(const Walker& W, Smem& S) {
+VMC_PHASE void wg_reorder(const Walker& W, Smem& S) {
   const int n = W.n;
   short* rp = (short*)S.A;
   short* cp = rp + align_up((size_t)n, 8);
@@ -81,6 +81,67 @@ __device__ inline void wg_reorder(const Walker& W, Smem& S) {
     W.colsite[k] = s;
     W.cpos[s] = k;
   }
+  __syncthreads();
+}
+
+// Exclusive prefix sum over n row lengths into ptr[0..n] (ptr[n] = total),
+// each thread owning a contiguous run of rows.
+__device__ inline void wg_exclusive_scan(const int* len, int* ptr, int n, Smem& S) {
+  int* sc = (int*)S.red;  // NT ints
+  const int chunk = (n + NT - 1) / NT;
+  const int b0 = threadIdx.x * chunk;
+  const int b1 = min(n, b0 + chunk);
+  int loc = 0;
+  for (int r = b0; r < b1; ++r) loc += len[r];
+  __syncthreads();
+  sc[threadIdx.x] = loc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int t = 0; t < NT; ++t) {
+      const int v = sc[t];
+      sc[t] = run;
+      run += v;
+    }
+    ptr[n] = run;
+  }
+  __syncthreads();
+  int run = sc[threadIdx.x];
+  for (int r = b0; r < b1; ++r) {
+    ptr[r] = run;
+    run += len[r];
+  }
+  __syncthreads();
+}
+
+// Compact CSR copies of L and of D^{-1}U for the triangular solves.
+__device__ inline void wg_pack_factors(const Walker& W, Smem& S) {
+  const int n = W.n, F = W.F;
+  wg_exclusive_scan(W.l_len, W.lp, n, S);
+  wg_exclusive_scan(W.u_len, W.up, n, S);
+  __threadfence_block();
+  __syncthreads();
+  for (int r = threadIdx.x; r < n; r += NT) {
+    const int tag = (r & (BLK - 1)) << 16;
+    int o = W.lp[r];
+    const int ll = W.l_len[r];
+    for (int e = 0; e < ll; ++e) {
+      W.lc[o + e] = tag | W.l_col[(size_t)r * F + e];
+      const double v = W.l_val[(size_t)r * F + e];
+      W.lv64[o + e] = v;
+      W.lv32[o + e] = (float)v;
+    }
+    o = W.up[r];
+    const int ul = W.u_len[r];
+    const double dinv = W.u_dinv[r];
+    for (int e = 0; e < ul; ++e) {
+      W.uc[o + e] = tag | W.u_col[(size_t)r * F + e];
+      const double v = W.u_val[(size_t)r * F + e] * dinv;
+      W.uv64[o + e] = v;
+      W.uv32[o + e] = (float)v;
+    }
+  }
+  __threadfence_block();
   __syncthreads();
 }
 
@@ -171,7 +232,7 @@ __device__ inline void ilu_fetch_pending(const Walker& W, IluCand& C, int ncand,
   }
 }
 
-__device__ inline int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
+VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
   const int n = W.n;
   const int F = W.F;
   const int pfill = ilutp_row_cap_extra(W, P, S);
@@ -451,24 +512,19 @@ __device__ inline int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
   for (int i = threadIdx.x; i < n; i += NT) {
     const int ul = W.u_len[i];
     int* uc = W.u_col + (size_t)i * F;
-    double* uv = W.u_val + (size_t)i * F;
     const double d = W.u_diag[i];
     const double dinv = 1.0 / d;
     W.u_dinv[i] = dinv;
     W.u_dinv32[i] = (float)dinv;
-    for (int e = 0; e < ul; ++e) {
-      uc[e] = pinv[uc[e]];
-      const double s = uv[e] * dinv;
-      W.us_val[(size_t)i * F + e] = s;
-      W.us_val32[(size_t)i * F + e] = (float)s;
-    }
-    const int ll = W.l_len[i];
-    for (int e = 0; e < ll; ++e) W.l_val32[(size_t)i * F + e] = (float)W.l_val[(size_t)i * F + e];
+    for (int e = 0; e < ul; ++e) uc[e] = pinv[uc[e]];
     const int al = W.a_len[i];
     int* ac = W.a_col + (size_t)i * W.W;
     for (int e = 0; e < al; ++e) ac[e] = pinv[ac[e]];
     W.ilu_q[i] = q[i];
   }
+  __threadfence_block();
+  __syncthreads();
+  wg_pack_factors(W, S);
   // colsite_new[k] = colsite_old[q[k]]; cpos[s] = pinv[cpos[s]]
   __syncthreads();
   int* tmp = (int*)wv;  // reuse the work row (n ints fit in n doubles)

@@ -373,7 +373,7 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
     int Wc = p->row_cap > 0 ? p->row_cap
                             : lattice_bound(in.cutoff + in.site_margin + 0.8660254037844387 * in.a, in.a);
     Wc = std::min(Wc, n);
-    Wc = (Wc + 3) / 4 * 4;  // 16-byte aligned rows for vector loads
+    Wc = (Wc + 15) / 16 * 16;  // 64-byte aligned rows (whole cache lines, vector loads)
     W.W = Wc;
     W.F = std::min(n, Wc + (Wc + 1) / 2 + 2);
     W.UC = 2 * Wc;
@@ -393,9 +393,11 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
     size_t o_reo_row = add(nn * 4), o_reo_col = add(nn * 4);
     size_t o_alen = add(nn * 4), o_acol = add(nn * Wc * 4), o_aval = add(nn * Wc * 8), o_aval32 = add(nn * Wc * 4);
     const size_t F = W.F;
-    size_t o_llen = add(nn * 4), o_lcol = add(nn * F * 4), o_lval = add(nn * F * 8), o_lval32 = add(nn * F * 4);
+    size_t o_llen = add(nn * 4), o_lcol = add(nn * F * 4), o_lval = add(nn * F * 8);
     size_t o_ulen = add(nn * 4), o_ucol = add(nn * F * 4), o_uval = add(nn * F * 8), o_udiag = add(nn * 8);
-    size_t o_usval = add(nn * F * 8), o_usval32 = add(nn * F * 4), o_udinv = add(nn * 8), o_udinv32 = add(nn * 4);
+    size_t o_udinv = add(nn * 8), o_udinv32 = add(nn * 4);
+    size_t o_lp = add((nn + 1) * 4), o_lc = add(nn * F * 4), o_lv64 = add(nn * F * 8), o_lv32 = add(nn * F * 4);
+    size_t o_up = add((nn + 1) * 4), o_uc = add(nn * F * 4), o_uv64 = add(nn * F * 8), o_uv32 = add(nn * F * 4);
     size_t o_q = add(nn * 4);
     size_t o_Z64 = p->precision == VMC_PREC_FP64 ? add((size_t)mm * nn * 8) : 0;
     size_t o_Z32 = p->precision == VMC_PREC_MIXED ? add((size_t)mm * nn * 4) : 0;
@@ -410,56 +412,62 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
     c->arenas.push_back(arena);
     if (hipMemset(arena, 0, off) != hipSuccess) return fail(VMC_EHIP, "memset failed");
     char* b = (char*)arena;
-    W.sites = (const double*)(b + o_sites);
-    W.sigma = (const double*)(b + o_sigma);
-    W.pos = (double*)(b + o_pos);
-    W.rowperm = (int*)(b + o_rowperm);
-    W.rpos = (int*)(b + o_rpos);
-    W.cpos = (int*)(b + o_cpos);
-    W.colsite = (int*)(b + o_colsite);
-    W.reo_row = (int*)(b + o_reo_row);
-    W.reo_col = (int*)(b + o_reo_col);
-    W.a_len = (int*)(b + o_alen);
-    W.a_col = (int*)(b + o_acol);
-    W.a_val = (double*)(b + o_aval);
-    W.a_val32 = (float*)(b + o_aval32);
-    W.l_len = (int*)(b + o_llen);
-    W.l_col = (int*)(b + o_lcol);
-    W.l_val = (double*)(b + o_lval);
-    W.l_val32 = (float*)(b + o_lval32);
-    W.u_len = (int*)(b + o_ulen);
-    W.u_col = (int*)(b + o_ucol);
-    W.u_val = (double*)(b + o_uval);
-    W.u_diag = (double*)(b + o_udiag);
-    W.us_val = (double*)(b + o_usval);
-    W.us_val32 = (float*)(b + o_usval32);
-    W.u_dinv = (double*)(b + o_udinv);
-    W.u_dinv32 = (float*)(b + o_udinv32);
-    W.ilu_q = (int*)(b + o_q);
-    W.Z64 = p->precision == VMC_PREC_FP64 ? (double*)(b + o_Z64) : nullptr;
-    W.Z32 = p->precision == VMC_PREC_MIXED ? (float*)(b + o_Z32) : nullptr;
-    W.up_len = (int*)(b + o_uplen);
-    W.up_col = (int*)(b + o_upcol);
-    W.up_val = (double*)(b + o_upval);
-    W.up_val32 = (float*)(b + o_upval32);
-    W.T = (double*)(b + o_T);
-    W.V = (void*)(b + o_V);
-    W.Xp = (void*)(b + o_Xp);
-    W.wv = (void*)(b + o_wv);
-    W.zvec = (double*)(b + o_z);
-    W.rvec = (double*)(b + o_r);
-    W.new_col = (int*)(b + o_newcol);
-    W.new_val = (double*)(b + o_newval);
-    W.pu_col = (int*)(b + o_pucol);
-    W.pu_val = (double*)(b + o_puval);
+    W.sites = (decltype(W.sites))(b + o_sites);
+    W.sigma = (decltype(W.sigma))(b + o_sigma);
+    W.pos = (decltype(W.pos))(b + o_pos);
+    W.rowperm = (decltype(W.rowperm))(b + o_rowperm);
+    W.rpos = (decltype(W.rpos))(b + o_rpos);
+    W.cpos = (decltype(W.cpos))(b + o_cpos);
+    W.colsite = (decltype(W.colsite))(b + o_colsite);
+    W.reo_row = (decltype(W.reo_row))(b + o_reo_row);
+    W.reo_col = (decltype(W.reo_col))(b + o_reo_col);
+    W.a_len = (decltype(W.a_len))(b + o_alen);
+    W.a_col = (decltype(W.a_col))(b + o_acol);
+    W.a_val = (decltype(W.a_val))(b + o_aval);
+    W.a_val32 = (decltype(W.a_val32))(b + o_aval32);
+    W.l_len = (decltype(W.l_len))(b + o_llen);
+    W.l_col = (decltype(W.l_col))(b + o_lcol);
+    W.l_val = (decltype(W.l_val))(b + o_lval);
+    W.u_len = (decltype(W.u_len))(b + o_ulen);
+    W.u_col = (decltype(W.u_col))(b + o_ucol);
+    W.u_val = (decltype(W.u_val))(b + o_uval);
+    W.u_diag = (decltype(W.u_diag))(b + o_udiag);
+    W.u_dinv = (decltype(W.u_dinv))(b + o_udinv);
+    W.u_dinv32 = (decltype(W.u_dinv32))(b + o_udinv32);
+    W.lp = (decltype(W.lp))(b + o_lp);
+    W.lc = (decltype(W.lc))(b + o_lc);
+    W.lv64 = (decltype(W.lv64))(b + o_lv64);
+    W.lv32 = (decltype(W.lv32))(b + o_lv32);
+    W.up = (decltype(W.up))(b + o_up);
+    W.uc = (decltype(W.uc))(b + o_uc);
+    W.uv64 = (decltype(W.uv64))(b + o_uv64);
+    W.uv32 = (decltype(W.uv32))(b + o_uv32);
+    W.ilu_q = (decltype(W.ilu_q))(b + o_q);
+    W.Z64 = p->precision == VMC_PREC_FP64 ? (decltype(W.Z64))(b + o_Z64) : nullptr;
+    W.Z32 = p->precision == VMC_PREC_MIXED ? (decltype(W.Z32))(b + o_Z32) : nullptr;
+    W.up_len = (decltype(W.up_len))(b + o_uplen);
+    W.up_col = (decltype(W.up_col))(b + o_upcol);
+    W.up_val = (decltype(W.up_val))(b + o_upval);
+    W.up_val32 = (decltype(W.up_val32))(b + o_upval32);
+    W.T = (decltype(W.T))(b + o_T);
+    W.V = (decltype(W.V))(b + o_V);
+    W.Xp = (decltype(W.Xp))(b + o_Xp);
+    W.wv = (decltype(W.wv))(b + o_wv);
+    W.zvec = (decltype(W.zvec))(b + o_z);
+    W.rvec = (decltype(W.rvec))(b + o_r);
+    W.new_col = (decltype(W.new_col))(b + o_newcol);
+    W.new_val = (decltype(W.new_val))(b + o_newval);
+    W.pu_col = (decltype(W.pu_col))(b + o_pucol);
+    W.pu_val = (decltype(W.pu_val))(b + o_puval);
     // host-side initial data
     std::vector<int> ident(n);
     for (int k = 0; k < n; ++k) ident[k] = k;
     bool ok = true;
     ok &= hipMemcpy((void*)W.sites, in.sites, nn * 3 * 8, hipMemcpyHostToDevice) == hipSuccess;
     ok &= hipMemcpy((void*)W.sigma, in.sigma, nn * 8, hipMemcpyHostToDevice) == hipSuccess;
-    ok &= hipMemcpy(W.pos, in.pos0, nn * 3 * 8, hipMemcpyHostToDevice) == hipSuccess;
-    for (int* dst : {W.rowperm, W.rpos, W.cpos, W.colsite, W.reo_row, W.reo_col, W.ilu_q})
+    ok &= hipMemcpy((void*)W.pos, in.pos0, nn * 3 * 8, hipMemcpyHostToDevice) == hipSuccess;
+    for (void* dst : {(void*)W.rowperm, (void*)W.rpos, (void*)W.cpos, (void*)W.colsite, (void*)W.reo_row,
+                      (void*)W.reo_col, (void*)W.ilu_q})
       ok &= hipMemcpy(dst, ident.data(), nn * 4, hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) return fail(VMC_EHIP, "initial copy failed");
   }
@@ -671,22 +679,22 @@ vmc_status vmc_get_state(void* ctx, int32_t walker, const vmc_state_view* v) {
     if (!dst) return hipSuccess;
     return hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost);
   };
-  HIPCHK(c, cp(v->pos, W.pos, n * 3 * 8));
-  HIPCHK(c, cp(v->row_particle, W.rowperm, n * 4));
-  HIPCHK(c, cp(v->col_site, W.colsite, n * 4));
-  HIPCHK(c, cp(v->reorder_row, W.reo_row, n * 4));
-  HIPCHK(c, cp(v->reorder_col, W.reo_col, n * 4));
-  HIPCHK(c, cp(v->a_len, W.a_len, n * 4));
-  HIPCHK(c, cp(v->a_col, W.a_col, n * W.W * 4));
-  HIPCHK(c, cp(v->a_val, W.a_val, n * W.W * 8));
-  HIPCHK(c, cp(v->l_len, W.l_len, n * 4));
-  HIPCHK(c, cp(v->l_col, W.l_col, n * W.F * 4));
-  HIPCHK(c, cp(v->l_val, W.l_val, n * W.F * 8));
-  HIPCHK(c, cp(v->u_len, W.u_len, n * 4));
-  HIPCHK(c, cp(v->u_col, W.u_col, n * W.F * 4));
-  HIPCHK(c, cp(v->u_val, W.u_val, n * W.F * 8));
-  HIPCHK(c, cp(v->u_diag, W.u_diag, n * 8));
-  HIPCHK(c, cp(v->ilu_perm, W.ilu_q, n * 4));
+  HIPCHK(c, cp(v->pos, (const void*)W.pos, n * 3 * 8));
+  HIPCHK(c, cp(v->row_particle, (const void*)W.rowperm, n * 4));
+  HIPCHK(c, cp(v->col_site, (const void*)W.colsite, n * 4));
+  HIPCHK(c, cp(v->reorder_row, (const void*)W.reo_row, n * 4));
+  HIPCHK(c, cp(v->reorder_col, (const void*)W.reo_col, n * 4));
+  HIPCHK(c, cp(v->a_len, (const void*)W.a_len, n * 4));
+  HIPCHK(c, cp(v->a_col, (const void*)W.a_col, n * W.W * 4));
+  HIPCHK(c, cp(v->a_val, (const void*)W.a_val, n * W.W * 8));
+  HIPCHK(c, cp(v->l_len, (const void*)W.l_len, n * 4));
+  HIPCHK(c, cp(v->l_col, (const void*)W.l_col, n * W.F * 4));
+  HIPCHK(c, cp(v->l_val, (const void*)W.l_val, n * W.F * 8));
+  HIPCHK(c, cp(v->u_len, (const void*)W.u_len, n * 4));
+  HIPCHK(c, cp(v->u_col, (const void*)W.u_col, n * W.F * 4));
+  HIPCHK(c, cp(v->u_val, (const void*)W.u_val, n * W.F * 8));
+  HIPCHK(c, cp(v->u_diag, (const void*)W.u_diag, n * 8));
+  HIPCHK(c, cp(v->ilu_perm, (const void*)W.ilu_q, n * 4));
   if (v->step || v->n_updates) {
     WalkerState s;
     HIPCHK(c, hipMemcpy(&s, c->dS + walker, sizeof(s), hipMemcpyDeviceToHost));
