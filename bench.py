@@ -3,10 +3,13 @@
 One bench "step" is one Metropolis step of every walker in the batch (proposal,
 Slater row, ILUTP-preconditioned GMRES ratio, decision, row replacement,
 preconditioner update, and any triggered reorder/refactor), i.e. `walkers`
-det-ratio steps.  The timed region is one launch of the persistent kernel
-covering K such steps, bracketed by device synchronisations and timed with
-events on the stream the kernel runs on.  Set-up (context creation, initial
-reorder and ILUTP) and W warm-up steps are outside the timed region.
+det-ratio steps.  The timed region is K such steps, run as launches of the
+persistent kernel of `chunk` steps each (by default one launch of K steps),
+bracketed by device synchronisations and timed with events on the stream the
+kernel runs on.  Set-up (context creation, initial reorder and ILUTP) and W
+warm-up steps, launched in the same chunks, are outside the timed region; with
+the default W = K every launch of the kernel has the same size, so a profiler's
+per-launch average is the timed launch's duration.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -56,6 +59,22 @@ def algorithmic_bytes(stats0, stats1, nnz, n, mixed: bool):
     return tot
 
 
+def measured_traffic(path, workload, chunk, walkers, m_max):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy
+    calibration), or None when that summary was taken on other kernel sources
+    or another launch configuration."""
+    from paper_1008_5113_amd.profiling import kernel_source_hash
+    f = os.path.join(ROOT, "profiles", f"k_run_{workload}_{path}_counters.json")
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        d = json.load(fh)
+    same = (d.get("source_hash") == kernel_source_hash()
+            and d.get("launch") == {"chunk": chunk, "walkers": walkers, "m_max": m_max})
+    return d["hbm_bytes_per_launch"] if same else None
+
+
 def factor_nnz(ctx, walkers):
     acc = np.zeros(3)
     for w in walkers:
@@ -64,7 +83,7 @@ def factor_nnz(ctx, walkers):
     return acc / len(walkers)
 
 
-def run_path(inst, precision, steps, warmup, walkers, stream_ptr, **kw):
+def run_path(inst, precision, steps, warmup, chunk, walkers, stream_ptr, **kw):
     import torch
     import paper_1008_5113_amd as vm
     t0 = time.time()
@@ -75,19 +94,24 @@ def run_path(inst, precision, steps, warmup, walkers, stream_ptr, **kw):
         f"{time.time() - t0:.1f}s")
     if warmup:
         t1 = time.time()
-        ctx.run_steps(warmup)
+        for _ in range(warmup // chunk):
+            ctx.run_steps(chunk)
         ctx.sync()
         log(f"precision={precision}: warm-up {warmup} steps {time.time() - t1:.1f}s")
     s0 = ctx.stats()
+    # every launch of the persistent kernel covers `chunk` steps of every walker;
+    # one event pair per launch, recorded on the stream the kernel runs on
     stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    nl = steps // chunk
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(nl + 1)]
     torch.cuda.synchronize()
-    ev0.record(stream)
-    ctx.run_steps(steps)
-    ev1.record(stream)
+    evs[0].record(stream)
+    for k in range(nl):
+        ctx.run_steps(chunk)
+        evs[k + 1].record(stream)
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
+    launch_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(nl)]
+    ms = evs[0].elapsed_time(evs[nl])
     ctx.sync()
     s1 = ctx.stats()
     nnz = factor_nnz(ctx, list(range(min(4, len(walkers)))))
@@ -101,13 +125,14 @@ def run_path(inst, precision, steps, warmup, walkers, stream_ptr, **kw):
     phase_us = {name: ph[k] / max(1, nsteps) / vm.vmcdet.WALL_CLOCK_HZ * 1e6
                 for k, name in enumerate(vm.vmcdet.PHASE_NAMES)}
     out = dict(
-        ms=ms, steps=nsteps, steps_per_s=nsteps / (ms / 1e3),
+        ms=ms, launches=nl, launch_ms_avg=float(np.mean(launch_ms)), steps=nsteps, steps_per_s=nsteps / (ms / 1e3),
         accept=d("accepted") / max(1, nsteps), iters_per_step=d("iters") / max(1, nsteps),
         inner_per_step=d("inner_solves") / max(1, nsteps), passes_per_step=d("refine_passes") / max(1, nsteps),
         reorders=d("reorders"), refactors=d("refactors"), nonconverged=d("nonconverged"),
         max_N=max(b["max_N"] for b in s1), nnz_per_row=(nnz / n).tolist(),
         phase_us_per_walker_step={k: round(v, 2) for k, v in phase_us.items()},
-        alg_bytes=bytes_, alg_gbs=bytes_ / (ms / 1e3) / 1e9,
+        alg_bytes=bytes_, alg_bytes_per_launch=bytes_ / nl,
+        alg_gbs=bytes_ / (sum(launch_ms) / 1e3) / 1e9,
         status=[b["status"] for b in s1 if b["status"] != 0][:4])
     ctx.close()
     return out
@@ -205,7 +230,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=400)
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="steps per launch of the persistent kernel (0: --steps, one timed launch)")
     ap.add_argument("--workload", default="mixed_n4000")
     ap.add_argument("--walkers", type=int, default=0, help="0: the workload's count")
     ap.add_argument("--paths", default="mixed,fp64")
@@ -229,6 +256,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}))
         return
+    if args.chunk <= 0:
+        args.chunk = args.steps
+    if args.steps % args.chunk or args.warmup % args.chunk:
+        ap.error("--steps and --warmup must be multiples of --chunk")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: walkers are independent chains and this build "
               "measures one GPU's share; use --gpus 1", file=sys.stderr)
@@ -254,7 +285,7 @@ def main():
         prec = vm.PREC_MIXED if path == "mixed" else vm.PREC_FP64
         log(f"path {path}: {nw} walkers, n={inst.systems[0].n}, {args.steps} timed steps")
         kw = {"m_max": args.m_max} if args.m_max else {}
-        results[path] = run_path(inst, prec, args.steps, args.warmup, walkers, stream_ptr, **kw)
+        results[path] = run_path(inst, prec, args.steps, args.warmup, args.chunk, walkers, stream_ptr, **kw)
         log(f"path {path}: {json.dumps(results[path])}")
     head = results.get("mixed") or results[next(iter(results))]
     headpath = "mixed" if "mixed" in results else next(iter(results))
@@ -279,8 +310,13 @@ def main():
     if "mixed" in results and "fp64" in results:
         out["mixed_over_fp64"] = results["mixed"]["steps_per_s"] / results["fp64"]["steps_per_s"]
     out["roofline"] = {"bound": "hbm", "achieved": head["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": head["alg_gbs"] / HBM_PEAK_GBS, "traffic": None,
-                       "kernel": "k_run (persistent fused step kernel)"}
+                       "frac": head["alg_gbs"] / HBM_PEAK_GBS,
+                       "traffic": measured_traffic(headpath, args.workload, args.chunk, nw,
+                                                   args.m_max or inst.params.m_max),
+                       "kernel": f"k_run<{1 if headpath == 'mixed' else 0}> (persistent fused step kernel), "
+                                 f"{args.chunk} steps x {nw} walkers per launch",
+                       "launch_ms_avg": head["launch_ms_avg"],
+                       "alg_bytes_per_launch": head["alg_bytes_per_launch"]}
     if not args.no_cpu_baseline:
         log(f"cpu baseline: {args.cpu_procs} processes x {args.cpu_steps} oracle steps")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_procs, args.cpu_steps)

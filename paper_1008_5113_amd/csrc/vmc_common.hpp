@@ -116,8 +116,16 @@ struct PhaseClock {
 // ---------------------------------------------------------------------------
 // Reductions (deterministic: fixed butterfly order, identical in every lane)
 // ---------------------------------------------------------------------------
-__device__ inline int lane_id() { return threadIdx.x & 63; }
-__device__ inline int wave_id() { return threadIdx.x >> 6; }
+// Thread index as a value the optimizer cannot see through.  Index arithmetic
+// derived from it is then recomputed inside each phase instead of being hoisted
+// out of the step and Krylov loops and held in registers across every phase.
+__device__ inline int vmc_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+__device__ inline int lane_id() { return vmc_tid() & 63; }
+__device__ inline int wave_id() { return vmc_tid() >> 6; }
 
 // DPP lane moves (VALU, no LDS traffic).  quad_perm xor 1 / xor 2 and the
 // row mirrors stay inside a 16-lane row; row_shl:4 reads lane+4 of the row.

@@ -97,7 +97,7 @@ template <typename KT, bool FORWARD>
 VMC_PHASE void wg_trisolve_rows(const Walker& W, const int* ptr, const int* cols, const KT* vals,
                                         const KT* aux, int unit, KT* xs, KT* D, KT* st) {
   const int n = W.n;
-  const int rr = threadIdx.x >> 3, sub = threadIdx.x & 7;
+  const int rr = vmc_tid() >> 3, sub = vmc_tid() & 7;
   const int nb = (n + BLK - 1) / BLK;
   auto row_of = [&](int t) { return (t >= 0 && t < nb) ? (FORWARD ? t : nb - 1 - t) * BLK + rr : -1; };
   auto aux_of = [&](int r) -> KT {
@@ -196,7 +196,7 @@ VMC_PHASE void wg_updates(const Walker& W, int m, int mmax, KT* xs, Smem& S) {
   const int n = W.n;
   const KT* upv = Fac<KT>::upval(W);
   for (int s0 = 0; s0 < m; s0 += NT / 4) {
-    const int s = s0 + (threadIdx.x >> 2), part = threadIdx.x & 3;
+    const int s = s0 + (vmc_tid() >> 2), part = vmc_tid() & 3;
     KT acc = 0;
     if (s < m) {
       const int len = W.up_len[s];
@@ -209,7 +209,7 @@ VMC_PHASE void wg_updates(const Walker& W, int m, int mmax, KT* xs, Smem& S) {
     if (s < m && part == 0) S.gb[s] = (double)acc;
   }
   __syncthreads();
-  for (int s = threadIdx.x; s < m; s += NT) {
+  for (int s = vmc_tid(); s < m; s += NT) {
     const double* Gs = W.T + (size_t)s * mmax;
     double c = 0.0;
 #pragma unroll 8
@@ -223,7 +223,7 @@ VMC_PHASE void wg_updates(const Walker& W, int m, int mmax, KT* xs, Smem& S) {
     KT xr[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-      const int r = rb + k * NT + threadIdx.x;
+      const int r = rb + k * NT + vmc_tid();
       xr[k] = (r < n) ? xs[r] : (KT)0;
     }
     int s = 0;
@@ -232,7 +232,7 @@ VMC_PHASE void wg_updates(const Walker& W, int m, int mmax, KT* xs, Smem& S) {
       const KT* z0 = Z + (size_t)s * n;
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
-        const int r = rb + k * NT + threadIdx.x;
+        const int r = rb + k * NT + vmc_tid();
         if (r < n) {
           const KT a0 = z0[r], a1 = z0[n + r], a2 = z0[2 * (size_t)n + r], a3 = z0[3 * (size_t)n + r];
           xr[k] -= a0 * c0 + a1 * c1 + a2 * c2 + a3 * c3;
@@ -244,13 +244,13 @@ VMC_PHASE void wg_updates(const Walker& W, int m, int mmax, KT* xs, Smem& S) {
       const KT* z0 = Z + (size_t)s * n;
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
-        const int r = rb + k * NT + threadIdx.x;
+        const int r = rb + k * NT + vmc_tid();
         if (r < n) xr[k] -= z0[r] * c0;
       }
     }
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-      const int r = rb + k * NT + threadIdx.x;
+      const int r = rb + k * NT + vmc_tid();
       if (r < n) xs[r] = xr[k];
     }
   }
@@ -329,7 +329,7 @@ template <typename VT, typename XT, typename AT, typename OT>
 __device__ inline double wg_rows_apply(const Walker& W, const VT* aval, const XT* x, OT* out, int unit,
                                        bool resid) {
   const int n = W.n, Wc = W.W;
-  const int rr = threadIdx.x >> 3, sub = threadIdx.x & 7;
+  const int rr = vmc_tid() >> 3, sub = vmc_tid() & 7;
   double sq = 0.0;
   int l0 = (rr < n) ? W.a_len[rr] : 0;
   int l1 = (rr + BLK < n) ? W.a_len[rr + BLK] : 0;
@@ -380,7 +380,7 @@ VMC_PHASE double wg_resid64(const Walker& W, const double* z, int unit, double* 
   double sq;
   if ((size_t)n * 8 <= stage_bytes) {
     double* zs = (double*)S.A;
-    for (int r = threadIdx.x; r < n; r += NT) zs[r] = z[r];
+    for (int r = vmc_tid(); r < n; r += NT) zs[r] = z[r];
     __syncthreads();
     sq = wg_rows_apply<double, double, double, double>(W, W.a_val, zs, rv, unit, true);
   } else {
@@ -397,12 +397,12 @@ __device__ inline void wg_dots(const KT* w, const KT* V, int n, int cnt, double*
   for (int i = 0; i < cnt; ++i) {
     KT acc = 0;
     const KT* vi = V + (size_t)i * n;
-    for (int r = threadIdx.x; r < n; r += NT) acc += w[r] * vi[r];
+    for (int r = vmc_tid(); r < n; r += NT) acc += w[r] * vi[r];
     const double s = wave_sum((double)acc);
     if (lane_id() == 0) S.red[i * NWAVE + wave_id()] = s;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < cnt; i += NT) {
+  for (int i = vmc_tid(); i < cnt; i += NT) {
     double s = 0.0;
     for (int k = 0; k < NWAVE; ++k) s += S.red[i * NWAVE + k];
     out[i] = s;
@@ -435,11 +435,11 @@ __device__ inline SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, 
   const bool unit_rhs = (rhs64 == nullptr);
   {
     KT* D = xs + align_up((size_t)n, 4);
-    for (int e = threadIdx.x; e < BLK * BLK; e += NT) D[e] = (KT)0;
+    for (int e = vmc_tid(); e < BLK * BLK; e += NT) D[e] = (KT)0;
   }
-  for (int r = threadIdx.x; r < n; r += NT)
+  for (int r = vmc_tid(); r < n; r += NT)
     V[r] = unit_rhs ? (KT)(r == unit ? 1 : 0) : (KT)(rhs64[r] / beta);
-  if (threadIdx.x == 0) S.gg[0] = 1.0;
+  if (vmc_tid() == 0) S.gg[0] = 1.0;
   __syncthreads();
   double N = 0.0;
   int k = 0;
@@ -451,13 +451,13 @@ __device__ inline SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, 
     KT* xp = Xp + (size_t)j * n;
     PhaseClock pc;
     pc.start();
-    for (int r = threadIdx.x; r < n; r += NT) xp[r] = xs[r];
+    for (int r = vmc_tid(); r < n; r += NT) xp[r] = xs[r];
     wg_spmv<KT>(W, aval, xs, w);
     __syncthreads();
     pc.stop(S, PH_SPMV);
     // effective stability: ||v_j - A M v_j||
     double nl = 0.0;
-    for (int r = threadIdx.x; r < n; r += NT) {
+    for (int r = vmc_tid(); r < n; r += NT) {
       const double d = (double)vj[r] - (double)w[r];
       nl += d * d;
     }
@@ -466,7 +466,7 @@ __device__ inline SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, 
     // classical Gram-Schmidt, twice
     double* h = S.hb;
     wg_dots<KT>(w, V, n, j + 1, h, S);
-    for (int r = threadIdx.x; r < n; r += NT) {
+    for (int r = vmc_tid(); r < n; r += NT) {
       KT x = w[r];
       for (int i = 0; i <= j; ++i) x -= (KT)h[i] * V[(size_t)i * n + r];
       w[r] = x;
@@ -475,7 +475,7 @@ __device__ inline SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, 
     double* h2 = S.yb;
     wg_dots<KT>(w, V, n, j + 1, h2, S);
     double nw = 0.0;
-    for (int r = threadIdx.x; r < n; r += NT) {
+    for (int r = vmc_tid(); r < n; r += NT) {
       KT x = w[r];
       for (int i = 0; i <= j; ++i) x -= (KT)h2[i] * V[(size_t)i * n + r];
       w[r] = x;
@@ -484,8 +484,8 @@ __device__ inline SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, 
     const double hn = sqrt(wg_sum(nw, S.red));
     KT* vn = V + (size_t)(j + 1) * n;
     const KT inv = (hn > 0.0) ? (KT)(1.0 / hn) : (KT)0;
-    for (int r = threadIdx.x; r < n; r += NT) vn[r] = w[r] * inv;
-    if (threadIdx.x == 0) {
+    for (int r = vmc_tid(); r < n; r += NT) vn[r] = w[r] * inv;
+    if (vmc_tid() == 0) {
       double* col = S.hb;
       for (int i = 0; i <= j; ++i) col[i] += h2[i];
       col[j + 1] = hn;
@@ -520,7 +520,7 @@ __device__ inline SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, 
   // y = R^{-1} g, z (+)= scale * sum y_i Xp_i
   PhaseClock pz;
   pz.start();
-  if (threadIdx.x == 0) {
+  if (vmc_tid() == 0) {
     for (int i = k - 1; i >= 0; --i) {
       double s = S.gg[i];
       for (int l = i + 1; l < k; ++l) s -= S.rp[(size_t)l * (l + 1) / 2 + i] * S.yb[l];
@@ -529,7 +529,7 @@ __device__ inline SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, 
     for (int i = 0; i < k; ++i) S.yb[i] *= scale;
   }
   __syncthreads();
-  for (int r = threadIdx.x; r < n; r += NT) {
+  for (int r = vmc_tid(); r < n; r += NT) {
     double acc = zinit ? 0.0 : z[r];
     for (int i = 0; i < k; ++i) acc += S.yb[i] * (double)Xp[(size_t)i * n + r];
     z[r] = acc;
@@ -547,7 +547,7 @@ __device__ inline SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, 
 // ratio = 1 + u^T z (FP64), u = pending update (column positions).
 __device__ inline double wg_ratio(const Walker& W, int ulen, const double* z, Smem& S) {
   double acc = 0.0;
-  for (int e = threadIdx.x; e < ulen; e += NT) acc += W.pu_val[e] * z[W.pu_col[e]];
+  for (int e = vmc_tid(); e < ulen; e += NT) acc += W.pu_val[e] * z[W.pu_col[e]];
   return 1.0 + wg_sum(acc, S.red);
 }
 

@@ -24,7 +24,7 @@ __device__ inline int wg_build_all_rows(const Walker& W, Smem& S) {
   __syncthreads();
   int flag = S.ic[0];
   __syncthreads();
-  if (threadIdx.x == 0) S.ic[0] = 0;
+  if (vmc_tid() == 0) S.ic[0] = 0;
   __syncthreads();
   return flag ? WST_CAPACITY : WST_OK;
 }
@@ -39,14 +39,14 @@ VMC_PHASE void wg_reorder(const Walker& W, Smem& S) {
   const int n = W.n;
   short* rp = (short*)S.A;
   short* cp = rp + align_up((size_t)n, 8);
-  for (int k = threadIdx.x; k < n; k += NT) { rp[k] = (short)k; cp[k] = (short)k; }
+  for (int k = vmc_tid(); k < n; k += NT) { rp[k] = (short)k; cp[k] = (short)k; }
   __syncthreads();
   for (int i = 0; i < n - 1; ++i) {
     const int pi = rp[i];
     const double rx = W.pos[3 * pi], ry = W.pos[3 * pi + 1], rz = W.pos[3 * pi + 2];
     double best = INFINITY;
     int bj = 0x7fffffff;
-    for (int j = i + threadIdx.x; j < n; j += NT) {
+    for (int j = i + vmc_tid(); j < n; j += NT) {
       double dx;
       double d2 = dist2_xyz(rx, ry, rz, W.sites + 3 * (size_t)cp[j], W.box, &dx);
       if (d2 < best) { best = d2; bj = j; }
@@ -54,14 +54,14 @@ VMC_PHASE void wg_reorder(const Walker& W, Smem& S) {
     wg_argmin(best, bj, S.red);
     if (bj != i) {
       __syncthreads();
-      if (threadIdx.x == 0) { short t = cp[i]; cp[i] = cp[bj]; cp[bj] = t; }
+      if (vmc_tid() == 0) { short t = cp[i]; cp[i] = cp[bj]; cp[bj] = t; }
       __syncthreads();
       continue;
     }
     const double* Zi = W.sites + 3 * (size_t)cp[i];
     best = INFINITY;
     int bk = 0x7fffffff;
-    for (int k = i + threadIdx.x; k < n; k += NT) {
+    for (int k = i + vmc_tid(); k < n; k += NT) {
       const int pk = rp[k];
       double dx;
       double d2 = dist2_xyz(W.pos[3 * pk], W.pos[3 * pk + 1], W.pos[3 * pk + 2], Zi, W.box, &dx);
@@ -69,10 +69,10 @@ VMC_PHASE void wg_reorder(const Walker& W, Smem& S) {
     }
     wg_argmin(best, bk, S.red);
     __syncthreads();
-    if (bk != i && threadIdx.x == 0) { short t = rp[i]; rp[i] = rp[bk]; rp[bk] = t; }
+    if (bk != i && vmc_tid() == 0) { short t = rp[i]; rp[i] = rp[bk]; rp[bk] = t; }
     __syncthreads();
   }
-  for (int k = threadIdx.x; k < n; k += NT) {
+  for (int k = vmc_tid(); k < n; k += NT) {
     const int p = rp[k], s = cp[k];
     W.reo_row[k] = p;
     W.reo_col[k] = s;
@@ -89,14 +89,14 @@ VMC_PHASE void wg_reorder(const Walker& W, Smem& S) {
 __device__ inline void wg_exclusive_scan(const int* len, int* ptr, int n, Smem& S) {
   int* sc = (int*)S.red;  // NT ints
   const int chunk = (n + NT - 1) / NT;
-  const int b0 = threadIdx.x * chunk;
+  const int b0 = vmc_tid() * chunk;
   const int b1 = min(n, b0 + chunk);
   int loc = 0;
   for (int r = b0; r < b1; ++r) loc += len[r];
   __syncthreads();
-  sc[threadIdx.x] = loc;
+  sc[vmc_tid()] = loc;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (vmc_tid() == 0) {
     int run = 0;
     for (int t = 0; t < NT; ++t) {
       const int v = sc[t];
@@ -106,7 +106,7 @@ __device__ inline void wg_exclusive_scan(const int* len, int* ptr, int n, Smem& 
     ptr[n] = run;
   }
   __syncthreads();
-  int run = sc[threadIdx.x];
+  int run = sc[vmc_tid()];
   for (int r = b0; r < b1; ++r) {
     ptr[r] = run;
     run += len[r];
@@ -121,7 +121,7 @@ __device__ inline void wg_pack_factors(const Walker& W, Smem& S) {
   wg_exclusive_scan(W.u_len, W.up, n, S);
   __threadfence_block();
   __syncthreads();
-  for (int r = threadIdx.x; r < n; r += NT) {
+  for (int r = vmc_tid(); r < n; r += NT) {
     const int tag = (r & (BLK - 1)) << 16;
     int o = W.lp[r];
     const int ll = W.l_len[r];
@@ -155,7 +155,7 @@ __device__ inline int ilutp_row_cap_extra(const Walker& W, const DevParams& P, S
   // p = ceil(nnz(A) / (2n)) unless given
   if (P.lfil >= 0) return P.lfil;
   int s = 0;
-  for (int i = threadIdx.x; i < W.n; i += NT) s += W.a_len[i];
+  for (int i = vmc_tid(); i < W.n; i += NT) s += W.a_len[i];
   double tot = wg_sum((double)s, S.red);
   return (int)ceil(tot / (2.0 * W.n));
 }
@@ -175,7 +175,7 @@ struct IluCand {
 constexpr int ST_UNFETCHED = -1;
 constexpr int CAND_DONE = 32767;
 constexpr int ST_GLOBAL = -2;
-constexpr int STAGE_UNR = 16;
+constexpr int STAGE_UNR = 8;
 
 __device__ inline void ilu_fetch_pending(const Walker& W, IluCand& C, int ncand, int& stoff) {
   const int lane = lane_id();
@@ -253,12 +253,12 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
   C.scol = (short*)base;                    base += align_up((size_t)SCAP * 2, 16);
   C.sval = (double*)base;
 
-  for (int k = threadIdx.x; k < n; k += NT) {
+  for (int k = vmc_tid(); k < n; k += NT) {
     wv[k] = 0.0;
     pinv[k] = (short)k;
     q[k] = (short)k;
   }
-  for (int k = threadIdx.x; k < (n + 31) / 32; k += NT) pbits[k] = 0u;
+  for (int k = vmc_tid(); k < (n + 31) / 32; k += NT) pbits[k] = 0u;
   __syncthreads();
 
   int status = WST_OK;
@@ -502,14 +502,14 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) S.ic[1] = status;
+  if (vmc_tid() == 0) S.ic[1] = status;
   __syncthreads();
   status = S.ic[1];
   __syncthreads();
   if (status != WST_OK) return status;
 
   // Fold Q into the column numbering: label c -> position pinv[c].
-  for (int i = threadIdx.x; i < n; i += NT) {
+  for (int i = vmc_tid(); i < n; i += NT) {
     const int ul = W.u_len[i];
     int* uc = W.u_col + (size_t)i * F;
     const double d = W.u_diag[i];
@@ -528,9 +528,9 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
   // colsite_new[k] = colsite_old[q[k]]; cpos[s] = pinv[cpos[s]]
   __syncthreads();
   int* tmp = (int*)wv;  // reuse the work row (n ints fit in n doubles)
-  for (int k = threadIdx.x; k < n; k += NT) tmp[k] = W.colsite[q[k]];
+  for (int k = vmc_tid(); k < n; k += NT) tmp[k] = W.colsite[q[k]];
   __syncthreads();
-  for (int k = threadIdx.x; k < n; k += NT) {
+  for (int k = vmc_tid(); k < n; k += NT) {
     W.colsite[k] = tmp[k];
     W.cpos[tmp[k]] = k;
   }

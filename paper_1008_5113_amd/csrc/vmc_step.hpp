@@ -21,7 +21,7 @@ __device__ inline int wg_prepare(const Walker& W, Smem& S, int p, const double* 
   int* nc = (int*)(S.A + align_up((size_t)W.W * 4, 16) + (size_t)W.W * 8);
   double* nv = (double*)((char*)nc + align_up((size_t)W.W * 4, 16));
   const int lo = W.a_len[i];
-  for (int e = threadIdx.x; e < lo; e += NT) {
+  for (int e = vmc_tid(); e < lo; e += NT) {
     oc[e] = W.a_col[(size_t)i * W.W + e];
     ov[e] = W.a_val[(size_t)i * W.W + e];
   }
@@ -47,7 +47,7 @@ __device__ inline int wg_prepare(const Walker& W, Smem& S, int p, const double* 
   int ul = 0;
   if (st == WST_OK) {
     // u = new row - old row over the union of the two patterns (eq. (matrixUpdateU))
-    for (int e = threadIdx.x; e < cnt; e += NT) {
+    for (int e = vmc_tid(); e < cnt; e += NT) {
       const int c = nc[e];
       double vo = 0.0;
       for (int f = 0; f < lo; ++f)
@@ -164,17 +164,17 @@ __device__ inline void wg_append_update(const Walker& W, const DevParams& P, Sme
                                         int ulen) {
   const int n = W.n, mm = P.m_max;
   const double inv = 1.0 / ratio;
-  for (int r = threadIdx.x; r < n; r += NT) {
+  for (int r = vmc_tid(); r < n; r += NT) {
     const double zh = W.zvec[r] * inv;
     if (PREC == VMC_PREC_FP64) W.Z64[(size_t)s * n + r] = zh;
     else W.Z32[(size_t)s * n + r] = (float)zh;
   }
-  for (int e = threadIdx.x; e < ulen; e += NT) {
+  for (int e = vmc_tid(); e < ulen; e += NT) {
     W.up_col[(size_t)s * W.UC + e] = W.pu_col[e];
     W.up_val[(size_t)s * W.UC + e] = W.pu_val[e];
     W.up_val32[(size_t)s * W.UC + e] = (float)W.pu_val[e];
   }
-  if (threadIdx.x == 0) W.up_len[s] = ulen;
+  if (vmc_tid() == 0) W.up_len[s] = ulen;
   __threadfence_block();
   __syncthreads();
   // t_l = u_s^T zhat_l, l < s, in the precision the apply uses
@@ -190,7 +190,7 @@ __device__ inline void wg_append_update(const Walker& W, const DevParams& P, Sme
   }
   __syncthreads();
   // G[s][t] = -sum_{l=t}^{s-1} t_l G[l][t];  G[s][s] = 1
-  for (int t = threadIdx.x; t <= s; t += NT) {
+  for (int t = vmc_tid(); t <= s; t += NT) {
     double v = 1.0;
     if (t < s) {
       double acc = 0.0;
@@ -209,7 +209,7 @@ __device__ inline void wg_append_update(const Walker& W, const DevParams& P, Sme
 template <int PREC>
 __device__ inline void wg_det_ratio(const Walker& W, WalkerState* ws, const DevParams& P, Smem& S, int p,
                                     const double* rnew, double u_acc) {
-  if (threadIdx.x == 0) S.ic[8] = 0;
+  if (vmc_tid() == 0) S.ic[8] = 0;
   __syncthreads();
   int flags = 0;
   int st = wg_prepare(W, S, p, rnew);
@@ -232,7 +232,7 @@ __device__ inline void wg_det_ratio(const Walker& W, WalkerState* ws, const DevP
                 (navg >= P.iter_min_solves && (double)o.iters_first >= P.iter_factor * avg) ||
                 (P.force_reorder_every > 0 && ((g + 1) % P.force_reorder_every) == 0);
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (vmc_tid() == 0) {
       ws->avg_count = navg + 1;
       ws->avg_iters = avg + ((double)o.iters_first - avg) / (double)(navg + 1);
       ws->st_solves += 1;
@@ -243,7 +243,7 @@ __device__ inline void wg_det_ratio(const Walker& W, WalkerState* ws, const DevP
     if (trig) {
       flags |= VMC_FLAG_REORDERED;
       st = wg_reorder_refactor<PREC>(W, P, S);
-      if (threadIdx.x == 0) {
+      if (vmc_tid() == 0) {
         ws->m = 0;
         ws->st_reorders += 1;
         ws->st_refactors += 1;
@@ -255,7 +255,7 @@ __device__ inline void wg_det_ratio(const Walker& W, WalkerState* ws, const DevP
         i = S.ic[4];
         ulen = S.ic[6];
         o = wg_solve<PREC>(W, 0, P, S, i, ulen);
-        if (threadIdx.x == 0) {
+        if (vmc_tid() == 0) {
           ws->st_solves += 1;
           ws->st_inner += o.inner;
           ws->st_refine += o.passes;
@@ -267,7 +267,7 @@ __device__ inline void wg_det_ratio(const Walker& W, WalkerState* ws, const DevP
   if (st & WST_SINGULAR) flags |= VMC_FLAG_SINGULAR;
   if (st & WST_CAPACITY) flags |= VMC_FLAG_CAPACITY;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (vmc_tid() == 0) {
     ws->pend_valid = (st == WST_OK) ? 1 : 0;
     ws->pend_p = p;
     ws->pend_i = i;
@@ -305,13 +305,13 @@ __device__ inline void wg_accept(const Walker& W, WalkerState* ws, const DevPara
   pc.start();
   if (accept) {
     flags |= VMC_FLAG_ACCEPTED;
-    for (int e = threadIdx.x; e < newlen; e += NT) {
+    for (int e = vmc_tid(); e < newlen; e += NT) {
       W.a_col[(size_t)i * W.W + e] = W.new_col[e];
       const double v = W.new_val[e];
       W.a_val[(size_t)i * W.W + e] = v;
       W.a_val32[(size_t)i * W.W + e] = (float)v;
     }
-    if (threadIdx.x == 0) {
+    if (vmc_tid() == 0) {
       W.a_len[i] = newlen;
       W.pos[3 * p] = ws->pend_newpos[0];
       W.pos[3 * p + 1] = ws->pend_newpos[1];
@@ -325,18 +325,18 @@ __device__ inline void wg_accept(const Walker& W, WalkerState* ws, const DevPara
       st = wg_ilutp(W, P, S);
       pc.stop(S, PH_REFACTOR);
       flags |= VMC_FLAG_REFACTORED;
-      if (threadIdx.x == 0) {
+      if (vmc_tid() == 0) {
         ws->m = 0;
         ws->st_refactors += 1;
       }
     } else {
       wg_append_update<PREC>(W, P, S, m, ratio, ulen);
-      if (threadIdx.x == 0) ws->m = m + 1;
+      if (vmc_tid() == 0) ws->m = m + 1;
     }
   }
   pc.stop(S, PH_ACCEPT);
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (vmc_tid() == 0) {
     if (rec) {
       rec->step = ws->g;
       rec->walker = widx;

@@ -5,7 +5,8 @@
 ``rocprofv3 --kernel-trace --stats`` and ``rocprofv3 --pmc FETCH_SIZE`` /
 ``--pmc WRITE_SIZE`` wrote (for bench.py and for bench.py --copy-calibration),
 scales the counters by what they read for a plain 1 GiB device copy, and writes
-the per-launch figures of the timed k_run dispatch to a JSON file.  The JSON
+the per-launch figures of the step kernel (every launch covers the same number
+of steps) to a JSON file, with the launch configuration it was taken at.  The JSON
 records a hash of the kernel sources; bench.py reports the traffic only while
 the sources still hash the same.
 """
@@ -52,33 +53,96 @@ def _largest_dispatch(rows, name_part, prec=None):
     return best
 
 
-def summarize(trace, fetch, write, copy_fetch, copy_write, prec):
+def _dispatches(rows, name_part, prec=None):
+    out = []
+    for r in rows:
+        if name_part not in r["Kernel_Name"]:
+            continue
+        if prec is not None and f"<{prec}>" not in r["Kernel_Name"]:
+            continue
+        out.append(r)
+    return out
+
+
+def summarize(trace, fetch, write, copy_fetch, copy_write, prec, launch):
     cf = _largest_dispatch(_rows(copy_fetch, "counter_collection.csv"), "copyBuffer")[1]
     cw = _largest_dispatch(_rows(copy_write, "counter_collection.csv"), "copyBuffer")[1]
     fetch_scale = COPY_BYTES / (float(cf["Counter_Value"]) * 1024.0)
     write_scale = COPY_BYTES / (float(cw["Counter_Value"]) * 1024.0)
-    f = _largest_dispatch(_rows(fetch, "counter_collection.csv"), "k_run", prec)[1]
-    w = _largest_dispatch(_rows(write, "counter_collection.csv"), "k_run", prec)[1]
+    # every launch of the step kernel covers the same number of steps, so the
+    # per-launch figure is the mean over its dispatches
+    fr = _dispatches(_rows(fetch, "counter_collection.csv"), "k_run", prec)
+    wr = _dispatches(_rows(write, "counter_collection.csv"), "k_run", prec)
+    fetch_kib = sum(float(r["Counter_Value"]) for r in fr) / len(fr)
+    write_kib = sum(float(r["Counter_Value"]) for r in wr) / len(wr)
+    tr = _dispatches(_rows(trace, "kernel_trace.csv"), "k_run", prec)
+    durs = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in tr]
     stats = _rows(trace, "kernel_stats.csv")
-    trace_rows = _rows(trace, "kernel_trace.csv")
-    tr = _largest_dispatch(trace_rows, "k_run", prec)
-    out = {
+    return {
         "kernel": f"k_run<{prec}>",
         "source_hash": kernel_source_hash(),
-        "fetch_kib": float(f["Counter_Value"]),
-        "write_kib": float(w["Counter_Value"]),
+        "launch": launch,
+        "dispatches": {"trace": len(tr), "fetch": len(fr), "write": len(wr)},
+        "fetch_kib_per_launch": fetch_kib,
+        "write_kib_per_launch": write_kib,
         "fetch_scale": fetch_scale,
         "write_scale": write_scale,
-        "hbm_bytes": float(f["Counter_Value"]) * 1024.0 * fetch_scale
-        + float(w["Counter_Value"]) * 1024.0 * write_scale,
-        "counter_dispatch_ms": (int(f["End_Timestamp"]) - int(f["Start_Timestamp"])) / 1e6,
-        "trace_dispatch_ms": tr[0] / 1e6 if tr else None,
-        "vgpr": int(f["VGPR_Count"]),
-        "scratch": int(f["Scratch_Size"]),
-        "grid": int(f["Grid_Size"]),
-        "kernel_stats": [{k: s[k] for k in ("Name", "Calls", "AverageNs", "Percentage")} for s in stats[:8]],
+        "hbm_bytes_per_launch": fetch_kib * 1024.0 * fetch_scale + write_kib * 1024.0 * write_scale,
+        "trace_launch_ms_avg": sum(durs) / len(durs) / 1e6 if durs else None,
+        "counter_launch_ms_avg": sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in fr)
+        / len(fr) / 1e6,
+        "vgpr": int(fr[0]["VGPR_Count"]),
+        "scratch": int(fr[0]["Scratch_Size"]),
+        "grid": int(fr[0]["Grid_Size"]),
+        "kernel_stats": [{k: st[k] for k in ("Name", "Calls", "AverageNs", "Percentage")} for st in stats[:8]],
     }
-    return out
+
+
+def to_markdown(d, commands, bench_line=None):
+    """Short text summary of `summarize`'s result, with the commands that made it."""
+    L = [f"# {d['kernel']} — rocprofv3 summary", ""]
+    L.append(f"Kernel sources hash `{d['source_hash']}`; launch configuration {json.dumps(d['launch'])}.")
+    L.append("")
+    L.append("## Commands")
+    L.append("")
+    L.append("```")
+    L.extend(commands)
+    L.append("```")
+    L.append("")
+    L.append("## Kernel trace (`--kernel-trace --stats`)")
+    L.append("")
+    L.append("| kernel | calls | average ns | % |")
+    L.append("|---|---|---|---|")
+    for st in d["kernel_stats"]:
+        name = st["Name"].replace("(anonymous namespace)::", "").split("(vmc::")[0]
+        L.append(f"| `{name}` | {st['Calls']} | {float(st['AverageNs']):.0f} | {float(st['Percentage']):.2f} |")
+    L.append("")
+    L.append(f"Average {d['kernel']} launch: {d['trace_launch_ms_avg']:.1f} ms over {d['dispatches']['trace']} "
+             f"launches of the same size.")
+    L.append("")
+    L.append("## HBM traffic (`--pmc FETCH_SIZE`, then `--pmc WRITE_SIZE`)")
+    L.append("")
+    L.append("| quantity | value |")
+    L.append("|---|---|")
+    L.append(f"| FETCH_SIZE per launch (KiB) | {d['fetch_kib_per_launch']:.6g} |")
+    L.append(f"| WRITE_SIZE per launch (KiB) | {d['write_kib_per_launch']:.6g} |")
+    L.append(f"| copy calibration: bytes per FETCH_SIZE KiB / 1024 | {d['fetch_scale']:.4f} |")
+    L.append(f"| copy calibration: bytes per WRITE_SIZE KiB / 1024 | {d['write_scale']:.4f} |")
+    L.append(f"| HBM bytes per launch (scaled) | {d['hbm_bytes_per_launch']:.4g} |")
+    L.append(f"| launch duration under counters (ms) | {d['counter_launch_ms_avg']:.1f} |")
+    L.append(f"| VGPRs / scratch bytes per lane / grid | {d['vgpr']} / {d['scratch']} / {d['grid']} |")
+    if bench_line:
+        b = json.loads(bench_line)
+        rf = b.get("roofline", {})
+        L.append("")
+        L.append("## bench.py line of the same configuration")
+        L.append("")
+        L.append(f"value {b['value']:.0f} {b['unit']}; roofline achieved {rf.get('achieved', 0):.0f} GB/s "
+                 f"(frac {rf.get('frac', 0):.3f}); algorithmic bytes per launch "
+                 f"{rf.get('alg_bytes_per_launch', 0):.4g}; event-timed launch {rf.get('launch_ms_avg', 0):.1f} ms.")
+        if rf.get("alg_bytes_per_launch"):
+            L.append(f"Measured / algorithmic bytes = {d['hbm_bytes_per_launch'] / rf['alg_bytes_per_launch']:.3f}.")
+    return "\n".join(L) + "\n"
 
 
 def main():
@@ -88,13 +152,29 @@ def main():
     for k in ("trace", "fetch", "write", "copy_fetch", "copy_write"):
         s.add_argument("--" + k.replace("_", "-"), required=True)
     s.add_argument("--prec", type=int, default=1)
+    s.add_argument("--chunk", type=int, required=True, help="steps per launch in the profiled run")
+    s.add_argument("--walkers", type=int, required=True)
+    s.add_argument("--m-max", type=int, required=True)
     s.add_argument("--out-json", required=True)
+    s.add_argument("--out-md", default=None)
+    s.add_argument("--commands", default=None, help="text file holding the profiling commands")
+    s.add_argument("--bench-log", default=None, help="bench.py output of the same configuration")
     args = ap.parse_args()
     if args.cmd != "summarize":
         ap.error("summarize is the only command")
-    out = summarize(args.trace, args.fetch, args.write, args.copy_fetch, args.copy_write, args.prec)
+    launch = {"chunk": args.chunk, "walkers": args.walkers, "m_max": args.m_max}
+    out = summarize(args.trace, args.fetch, args.write, args.copy_fetch, args.copy_write, args.prec, launch)
     with open(args.out_json, "w") as f:
         json.dump(out, f, indent=1)
+    if args.out_md:
+        cmds = open(args.commands).read().splitlines() if args.commands else []
+        line = None
+        if args.bench_log:
+            for ln in open(args.bench_log):
+                if ln.startswith("{"):
+                    line = ln
+        with open(args.out_md, "w") as f:
+            f.write(to_markdown(out, cmds, line))
     print(json.dumps(out, indent=1))
 
 

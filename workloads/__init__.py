@@ -192,7 +192,9 @@ def mixed_n4000(n_walkers: int = 512) -> Instance:
     s = make_system((10, 20, 20), sigma=0.35, kind=ORB_GAUSS_PX, p_scale=0.1,
                     p_sigma=0.5, cutoff=2.5)
     ws = [Walker(0, initial_positions(s.sites, s.box, w, 0.3), w) for w in range(n_walkers)]
-    return Instance("mixed_n4000", [s], ws, Params(step=0.25, sweeps=30, mixed=True))
+    # m_max: the refactor period balancing the measured ILUTP cost against the
+    # growing cost of applying the stored updates
+    return Instance("mixed_n4000", [s], ws, Params(step=0.25, sweeps=30, mixed=True, m_max=128))
 
 
 def stress_n8192(n_walkers: int = 64) -> Instance:
