@@ -6,7 +6,7 @@
 namespace vmc {
 
 // Phase-level device functions (inlined into the fused kernels).
-#define VMC_PHASE __device__ inline
+#define VMC_PHASE __device__ __attribute__((always_inline)) inline
 
 // ---------------------------------------------------------------------------
 // Shared-memory layout.  Region A is a union of the phase-private buffers

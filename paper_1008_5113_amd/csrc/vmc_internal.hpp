@@ -104,13 +104,13 @@ struct Walker {
   double GAS* u_dinv;
   float GAS* u_dinv32;
   // compact CSR copies for the triangular solves, rebuilt after every
-  // factorisation; column word = (row & 63) << 16 | column position
+  // factorisation; 16-bit column positions
   int GAS* lp;                    // n+1
-  int GAS* lc;
+  unsigned short GAS* lc;
   double GAS* lv64;
   float GAS* lv32;
   int GAS* up;                    // n+1
-  int GAS* uc;
+  unsigned short GAS* uc;
   double GAS* uv64;               // D^{-1} U off-diagonal
   float GAS* uv32;
   int GAS* ilu_q;                 // last ILUTP column permutation (labels before it)

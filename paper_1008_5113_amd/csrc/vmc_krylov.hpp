@@ -31,7 +31,7 @@ template <> struct Fac<float> {
 // coefficient times x_k.  The coefficients are read in batches of 16 that are
 // issued one batch ahead of use, so LDS latency stays off the dependency chain.
 template <typename KT, bool FORWARD>
-__device__ inline KT block_chain(KT a, const KT* D) {
+VMC_PHASE KT block_chain(KT a, const KT* D) {
   constexpr int B = sizeof(KT) == 8 ? 8 : 16;  // coefficients per batch (register budget)
   const int lane = lane_id();
   KT d0[B], d1[B];
@@ -61,98 +61,99 @@ __device__ inline KT block_chain(KT a, const KT* D) {
   return a;
 }
 
-constexpr int PF = 4;          // entries per thread per row (8 threads per row)
-constexpr int COLMASK = 0xFFFF;
+constexpr int PF = 4;  // entries per thread per row (8 threads per row)
 
 __device__ inline bool is_far(bool forward, int c, int r0) {
   return forward ? (c < r0) : (c >= r0 + BLK);
 }
 
-// Triangular solve by 64-row blocks on the compact CSR factors.  8 threads per row hold up to PF
-// entries each in registers; row data is loaded two blocks ahead of use and
-// the row pointers three blocks ahead.
+// Triangular solve by 64-row blocks on the compact CSR factors.  8 threads
+// per row hold up to PF entries each in registers; rows longer than 8*PF
+// finish in a strided tail loop, which runs before the block's prefetch is
+// issued.  A block's row data is loaded two blocks ahead of its use and its row
+// pointers three blocks ahead.  The loads are branch-free (indices clamped to a
+// valid entry, selects applied at the use), and the block loop is unrolled by
+// three over a block count padded to a multiple of three, so the register sets
+// keep fixed roles and every path issues the same loads: no load is waited for
+// before its block comes up.
 template <typename KT>
 struct RowChunk {
+  int ok;       // row exists
   int len;
+  int start;
   int col[PF];
   KT val[PF];
-  KT aux;  // right-hand side (L) or inverse diagonal (U) of the row
+  KT aux;       // right-hand side (L) or inverse diagonal (U) as loaded
 };
 
-template <typename KT>
-__device__ inline void load_row_chunk(RowChunk<KT>& ch, int r, int n, int start, int len, const int* cols,
-                                      const KT* vals, int sub) {
-  ch.len = (r >= 0 && r < n) ? len : 0;
-#pragma unroll
-  for (int t = 0; t < PF; ++t) {
-    const int e = sub + 8 * t;
-    if (e < ch.len) {
-      ch.col[t] = cols[start + e] & COLMASK;
-      ch.val[t] = vals[start + e];
-    }
-  }
-}
-
 template <typename KT, bool FORWARD>
-VMC_PHASE void wg_trisolve_rows(const Walker& W, const int* ptr, const int* cols, const KT* vals,
-                                        const KT* aux, int unit, KT* xs, KT* D, KT* st) {
+VMC_PHASE void wg_trisolve_rows(const Walker& W, const int* ptr, const unsigned short* cols,
+                                const KT* vals, const KT* aux, int unit, KT* xs, KT* D, KT* st) {
   const int n = W.n;
   const int rr = vmc_tid() >> 3, sub = vmc_tid() & 7;
   const int nb = (n + BLK - 1) / BLK;
   auto row_of = [&](int t) { return (t >= 0 && t < nb) ? (FORWARD ? t : nb - 1 - t) * BLK + rr : -1; };
-  auto aux_of = [&](int r) -> KT {
-    if (r < 0 || r >= n) return (KT)0;
-    if (FORWARD) return aux ? aux[r] : (KT)(r == unit ? 1 : 0);
-    return aux[r];
-  };
-  auto ptr_of = [&](int t, int& a, int& b) {
+  int pa = 0, pb = 0, pok = 0;  // row pointers of the next block to load
+  auto load_ptr = [&](int t) {
     const int r = row_of(t);
-    if (r >= 0 && r < n) { a = ptr[r]; b = ptr[r + 1]; } else { a = 0; b = 0; }
+    pok = (r >= 0 && r < n);
+    const int rc = pok ? r : 0;
+    pa = ptr[rc];
+    pb = ptr[rc + 1];
   };
-  RowChunk<KT> c0, c1, c2;
-  int pa, pb, qa, qb;
-  ptr_of(0, pa, pb);
-  ptr_of(1, qa, qb);
-  load_row_chunk(c0, row_of(0), n, pa, pb - pa, cols, vals, sub);
-  c0.aux = aux_of(row_of(0));
-  load_row_chunk(c1, row_of(1), n, qa, qb - qa, cols, vals, sub);
-  c1.aux = aux_of(row_of(1));
-  int s2a, s2b;
-  ptr_of(2, s2a, s2b);
-  for (int t = 0; t < nb; ++t) {
-    const int r0 = (FORWARD ? t : nb - 1 - t) * BLK;
-    const int r = r0 + rr;
-    load_row_chunk(c2, row_of(t + 2), n, s2a, s2b - s2a, cols, vals, sub);
-    c2.aux = aux_of(row_of(t + 2));
-    ptr_of(t + 3, s2a, s2b);
-    KT acc = 0;
-    int dpos[PF];
+  auto load_chunk = [&](RowChunk<KT>& ch, int t) {
+    const int r = row_of(t);
+    ch.ok = pok;
+    ch.len = pok ? pb - pa : 0;
+    ch.start = pa;
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
       const int e = sub + 8 * k;
-      dpos[k] = -1;
-      if (e < c0.len) {
-        const int c = c0.col[k];
-        if (is_far(FORWARD, c, r0)) {
-          acc += c0.val[k] * xs[c];
-        } else {
-          dpos[k] = (c - r0) * BLK + rr;
-          D[dpos[k]] = c0.val[k];
+      const int idx = (e < ch.len) ? pa + e : 0;
+      ch.col[k] = cols[idx];
+      ch.val[k] = vals[idx];
+    }
+    if (aux) ch.aux = aux[pok ? r : 0];
+  };
+  auto block = [&](int t, const RowChunk<KT>& cur, RowChunk<KT>& ahead) {
+    const bool live = t < nb;  // the padding blocks only issue loads
+    const int r0 = (FORWARD ? t : nb - 1 - t) * BLK;
+    const int r = r0 + rr;
+    KT acc = 0;
+    int dpos[PF];
+    const bool tail = cur.len > 8 * PF;
+    if (live) {
+#pragma unroll
+      for (int k = 0; k < PF; ++k) {
+        const int e = sub + 8 * k;
+        dpos[k] = -1;
+        if (e < cur.len) {
+          const int c = cur.col[k];
+          if (is_far(FORWARD, c, r0)) {
+            acc += cur.val[k] * xs[c];
+          } else {
+            dpos[k] = (c - r0) * BLK + rr;
+            D[dpos[k]] = cur.val[k];
+          }
+        }
+      }
+      if (tail) {
+        for (int e = sub + 8 * PF; e < cur.len; e += 8) {
+          const int c = cols[cur.start + e];
+          const KT v = vals[cur.start + e];
+          if (is_far(FORWARD, c, r0)) acc += v * xs[c];
+          else D[(c - r0) * BLK + rr] = v;
         }
       }
     }
-    const int rs = (r < n) ? ptr[r] : 0;
-    for (int e = sub + 8 * PF; e < c0.len; e += 8) {
-      const int c = cols[rs + e] & COLMASK;
-      const KT v = vals[rs + e];
-      if (is_far(FORWARD, c, r0)) acc += v * xs[c];
-      else D[(c - r0) * BLK + rr] = v;
-    }
+    load_chunk(ahead, t + 2);
+    load_ptr(t + 3);
+    if (!live) return;
     acc = sum8(acc);
     if (sub == 0) {
       KT b;
-      if (FORWARD) b = c0.aux;
-      else b = (r < n) ? xs[r] * c0.aux : (KT)0;
+      if (FORWARD) b = !cur.ok ? (KT)0 : (aux ? cur.aux : (KT)(r == unit ? 1 : 0));
+      else b = cur.ok ? xs[r] * cur.aux : (KT)0;
       st[rr] = b - acc;
     }
     __syncthreads();
@@ -162,26 +163,37 @@ VMC_PHASE void wg_trisolve_rows(const Walker& W, const int* ptr, const int* cols
       if (r0 + lane_id() < n) xs[r0 + lane_id()] = a;
     }
     __syncthreads();
+    if (tail) {
+      // clear the row's whole tile row instead of re-reading its columns
+      for (int cc = sub; cc < BLK; cc += 8) D[cc * BLK + rr] = (KT)0;
+    } else {
 #pragma unroll
-    for (int k = 0; k < PF; ++k)
-      if (dpos[k] >= 0) D[dpos[k]] = (KT)0;
-    for (int e = sub + 8 * PF; e < c0.len; e += 8) {
-      const int c = cols[rs + e] & COLMASK;
-      if (!is_far(FORWARD, c, r0)) D[(c - r0) * BLK + rr] = (KT)0;
+      for (int k = 0; k < PF; ++k)
+        if (dpos[k] >= 0) D[dpos[k]] = (KT)0;
     }
-    c0 = c1;
-    c1 = c2;
+  };
+  RowChunk<KT> X0, X1, X2;
+  load_ptr(0);
+  load_chunk(X0, 0);
+  load_ptr(1);
+  load_chunk(X1, 1);
+  load_ptr(2);
+  const int nb3 = (nb + 2) / 3 * 3;
+  for (int t = 0; t < nb3; t += 3) {
+    block(t, X0, X2);
+    block(t + 1, X1, X0);
+    block(t + 2, X2, X1);
   }
 }
 
 template <typename KT>
-__device__ inline void wg_lsolve(const Walker& W, const KT* lval, const KT* rhs, int unit, KT* xs,
+VMC_PHASE void wg_lsolve(const Walker& W, const KT* lval, const KT* rhs, int unit, KT* xs,
                                  KT* D, KT* st) {
   wg_trisolve_rows<KT, true>(W, W.lp, W.lc, lval, rhs, unit, xs, D, st);
 }
 
 template <typename KT>
-__device__ inline void wg_usolve(const Walker& W, const KT* usval, const KT* dinv, KT* xs, KT* D,
+VMC_PHASE void wg_usolve(const Walker& W, const KT* usval, const KT* dinv, KT* xs, KT* D,
                                  KT* st) {
   wg_trisolve_rows<KT, false>(W, W.up, W.uc, usval, dinv, -1, xs, D, st);
 }
@@ -260,7 +272,7 @@ VMC_PHASE void wg_updates(const Walker& W, int m, int mmax, KT* xs, Smem& S) {
 // y = M v:  x = L^{-1} v, x = U^{-1} x, then the rank-one factors (all in the
 // column-position numbering, which already contains the ILUTP permutation).
 template <typename KT>
-__device__ inline void wg_precond(const Walker& W, int m, int mmax, const KT* vin, int unit, KT* xs,
+VMC_PHASE void wg_precond(const Walker& W, int m, int mmax, const KT* vin, int unit, KT* xs,
                                   Smem& S) {
   KT* D = xs + align_up((size_t)W.n, 4);
   KT* st = (KT*)S.stmp;
@@ -282,14 +294,14 @@ __device__ inline void wg_precond(const Walker& W, int m, int mmax, const KT* vi
 constexpr int SPMV_CH = 12;
 
 template <typename VT>
-__device__ inline void load_vals4(const VT* p, VT* v);
+VMC_PHASE void load_vals4(const VT* p, VT* v);
 template <>
-__device__ inline void load_vals4<float>(const float* p, float* v) {
+VMC_PHASE void load_vals4<float>(const float* p, float* v) {
   const float4 t = *reinterpret_cast<const float4*>(p);
   v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
 }
 template <>
-__device__ inline void load_vals4<double>(const double* p, double* v) {
+VMC_PHASE void load_vals4<double>(const double* p, double* v) {
   const double2 a = *reinterpret_cast<const double2*>(p);
   const double2 b = *reinterpret_cast<const double2*>(p + 2);
   v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
@@ -297,7 +309,7 @@ __device__ inline void load_vals4<double>(const double* p, double* v) {
 
 // acc = sum over the thread's chunk of row (ac, av, len) of av[e] * x[ac[e]]
 template <typename VT, typename XT, typename AT>
-__device__ inline AT row_chunk_dot(const int* ac, const VT* av, int len, int sub, const XT* x) {
+VMC_PHASE AT row_chunk_dot(const int* ac, const VT* av, int len, int sub, const XT* x) {
   const int e0 = sub * SPMV_CH;
   AT acc = 0;
   if (e0 < len) {
@@ -326,7 +338,7 @@ __device__ inline AT row_chunk_dot(const int* ac, const VT* av, int len, int sub
 // lengths loaded one pass ahead.  When out_resid is set, writes e_unit - A x
 // instead and returns the partial sum of squares.
 template <typename VT, typename XT, typename AT, typename OT>
-__device__ inline double wg_rows_apply(const Walker& W, const VT* aval, const XT* x, OT* out, int unit,
+VMC_PHASE double wg_rows_apply(const Walker& W, const VT* aval, const XT* x, OT* out, int unit,
                                        bool resid) {
   const int n = W.n, Wc = W.W;
   const int rr = vmc_tid() >> 3, sub = vmc_tid() & 7;
@@ -392,7 +404,7 @@ VMC_PHASE double wg_resid64(const Walker& W, const double* z, int unit, double* 
 
 // h[i] = sum_r w[r] V_i[r] for i < cnt (FP64 reduction), written to out[] (LDS).
 template <typename KT>
-__device__ inline void wg_dots(const KT* w, const KT* V, int n, int cnt, double* out, Smem& S) {
+VMC_PHASE void wg_dots(const KT* w, const KT* V, int n, int cnt, double* out, Smem& S) {
   __syncthreads();
   for (int i = 0; i < cnt; ++i) {
     KT acc = 0;
@@ -423,7 +435,7 @@ struct SolveOut {
 // (stabilityVecEq)).  b = e_unit (rhs64 == nullptr) or rhs64 / beta.  The
 // solution is accumulated in FP64: z (+)= scale * sum_j y_j (M v_j).
 template <typename KT>
-__device__ inline SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, Smem& S, int unit,
+VMC_PHASE SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, Smem& S, int unit,
                                     const double* rhs64, double beta, double tol, int maxit, double* z,
                                     double scale, bool zinit) {
   const int n = W.n;
@@ -545,7 +557,7 @@ __device__ inline SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, 
 }
 
 // ratio = 1 + u^T z (FP64), u = pending update (column positions).
-__device__ inline double wg_ratio(const Walker& W, int ulen, const double* z, Smem& S) {
+VMC_PHASE double wg_ratio(const Walker& W, int ulen, const double* z, Smem& S) {
   double acc = 0.0;
   for (int e = vmc_tid(); e < ulen; e += NT) acc += W.pu_val[e] * z[W.pu_col[e]];
   return 1.0 + wg_sum(acc, S.red);

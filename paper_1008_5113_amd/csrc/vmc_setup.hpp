@@ -7,7 +7,7 @@ namespace vmc {
 
 // Evaluate every row of A (row position i holds particle rowperm[i]; column
 // position of site s is cpos[s]).  One wave per row.  Returns WST_* bits.
-__device__ inline int wg_build_all_rows(const Walker& W, Smem& S) {
+VMC_PHASE int wg_build_all_rows(const Walker& W, Smem& S) {
   const int n = W.n;
   int bad = 0;
   for (int i = wave_id(); i < n; i += NWAVE) {
@@ -86,7 +86,7 @@ VMC_PHASE void wg_reorder(const Walker& W, Smem& S) {
 
 // Exclusive prefix sum over n row lengths into ptr[0..n] (ptr[n] = total),
 // each thread owning a contiguous run of rows.
-__device__ inline void wg_exclusive_scan(const int* len, int* ptr, int n, Smem& S) {
+VMC_PHASE void wg_exclusive_scan(const int* len, int* ptr, int n, Smem& S) {
   int* sc = (int*)S.red;  // NT ints
   const int chunk = (n + NT - 1) / NT;
   const int b0 = vmc_tid() * chunk;
@@ -115,18 +115,17 @@ __device__ inline void wg_exclusive_scan(const int* len, int* ptr, int n, Smem& 
 }
 
 // Compact CSR copies of L and of D^{-1}U for the triangular solves.
-__device__ inline void wg_pack_factors(const Walker& W, Smem& S) {
+VMC_PHASE void wg_pack_factors(const Walker& W, Smem& S) {
   const int n = W.n, F = W.F;
   wg_exclusive_scan(W.l_len, W.lp, n, S);
   wg_exclusive_scan(W.u_len, W.up, n, S);
   __threadfence_block();
   __syncthreads();
   for (int r = vmc_tid(); r < n; r += NT) {
-    const int tag = (r & (BLK - 1)) << 16;
     int o = W.lp[r];
     const int ll = W.l_len[r];
     for (int e = 0; e < ll; ++e) {
-      W.lc[o + e] = tag | W.l_col[(size_t)r * F + e];
+      W.lc[o + e] = (unsigned short)W.l_col[(size_t)r * F + e];
       const double v = W.l_val[(size_t)r * F + e];
       W.lv64[o + e] = v;
       W.lv32[o + e] = (float)v;
@@ -135,7 +134,7 @@ __device__ inline void wg_pack_factors(const Walker& W, Smem& S) {
     const int ul = W.u_len[r];
     const double dinv = W.u_dinv[r];
     for (int e = 0; e < ul; ++e) {
-      W.uc[o + e] = tag | W.u_col[(size_t)r * F + e];
+      W.uc[o + e] = (unsigned short)W.u_col[(size_t)r * F + e];
       const double v = W.u_val[(size_t)r * F + e] * dinv;
       W.uv64[o + e] = v;
       W.uv32[o + e] = (float)v;
@@ -151,7 +150,7 @@ __device__ inline void wg_pack_factors(const Walker& W, Smem& S) {
 // the column numbering: afterwards column position k holds label q[k] and A,
 // cpos/colsite are renumbered, so A (renumbered) ~ L U.
 // ---------------------------------------------------------------------------
-__device__ inline int ilutp_row_cap_extra(const Walker& W, const DevParams& P, Smem& S) {
+VMC_PHASE int ilutp_row_cap_extra(const Walker& W, const DevParams& P, Smem& S) {
   // p = ceil(nnz(A) / (2n)) unless given
   if (P.lfil >= 0) return P.lfil;
   int s = 0;
@@ -177,7 +176,7 @@ constexpr int CAND_DONE = 32767;
 constexpr int ST_GLOBAL = -2;
 constexpr int STAGE_UNR = 8;
 
-__device__ inline void ilu_fetch_pending(const Walker& W, IluCand& C, int ncand, int& stoff) {
+VMC_PHASE void ilu_fetch_pending(const Walker& W, IluCand& C, int ncand, int& stoff) {
   const int lane = lane_id();
   const int F = W.F;
   for (int s0 = 0; s0 < ncand; s0 += 64) {

@@ -11,7 +11,7 @@ namespace vmc {
 // New row of particle p at rnew (column positions) and u = new row - old row
 // (eq. (matrixUpdateU)), written to the walker's pending buffers.  Returns
 // WST_*; the row position and the lengths come back through S.ic[4..6].
-__device__ inline int wg_prepare(const Walker& W, Smem& S, int p, const double* rnew) {
+VMC_PHASE int wg_prepare(const Walker& W, Smem& S, int p, const double* rnew) {
   PhaseClock pc;
   pc.start();
   const int i = W.rpos[p];
@@ -101,7 +101,7 @@ struct StepSolve {
 
 // ratio = 1 + u^T z with A z = e_i (eq. (detRatioEq)).
 template <int PREC>
-__device__ inline StepSolve wg_solve(const Walker& W, int m, const DevParams& P, Smem& S, int i, int ulen) {
+VMC_PHASE StepSolve wg_solve(const Walker& W, int m, const DevParams& P, Smem& S, int i, int ulen) {
   StepSolve o;
   if (PREC == VMC_PREC_FP64) {
     SolveOut g = wg_gmres<double>(W, m, P, S, i, nullptr, 1.0, P.rtol, P.maxit, W.zvec, 1.0, true);
@@ -145,7 +145,7 @@ __device__ inline StepSolve wg_solve(const Walker& W, int m, const DevParams& P,
 
 // Geometric reorder, rebuild of A in the new order, ILUTP (Section 3.1/3.2).
 template <int PREC>
-__device__ inline int wg_reorder_refactor(const Walker& W, const DevParams& P, Smem& S) {
+VMC_PHASE int wg_reorder_refactor(const Walker& W, const DevParams& P, Smem& S) {
   PhaseClock pc;
   pc.start();
   wg_reorder(W, S);
@@ -160,7 +160,7 @@ __device__ inline int wg_reorder_refactor(const Walker& W, const DevParams& P, S
 // Append the rank-one factor of an accepted move (eq. (mkp1)): zhat = z/ratio,
 // u; G = (I + T)^{-1} gains a row.
 template <int PREC>
-__device__ inline void wg_append_update(const Walker& W, const DevParams& P, Smem& S, int s, double ratio,
+VMC_PHASE void wg_append_update(const Walker& W, const DevParams& P, Smem& S, int s, double ratio,
                                         int ulen) {
   const int n = W.n, mm = P.m_max;
   const double inv = 1.0 / ratio;
@@ -207,7 +207,7 @@ __device__ inline void wg_append_update(const Walker& W, const DevParams& P, Sme
 // Section 4: N > n_thresh, first solve not converged, or iterations >=
 // iter_factor * running average.  Leaves the pending state in the walker.
 template <int PREC>
-__device__ inline void wg_det_ratio(const Walker& W, WalkerState* ws, const DevParams& P, Smem& S, int p,
+VMC_PHASE void wg_det_ratio(const Walker& W, WalkerState* ws, const DevParams& P, Smem& S, int p,
                                     const double* rnew, double u_acc) {
   if (vmc_tid() == 0) S.ic[8] = 0;
   __syncthreads();
@@ -294,7 +294,7 @@ __device__ inline void wg_det_ratio(const Walker& W, WalkerState* ws, const DevP
 
 // Commit (accept != 0) or discard the pending move; advance the step counter.
 template <int PREC>
-__device__ inline void wg_accept(const Walker& W, WalkerState* ws, const DevParams& P, Smem& S, int accept,
+VMC_PHASE void wg_accept(const Walker& W, WalkerState* ws, const DevParams& P, Smem& S, int accept,
                                  int widx, vmc_step_record* rec) {
   const int p = ws->pend_p, i = ws->pend_i;
   const int newlen = ws->pend_newlen, ulen = ws->pend_ulen;

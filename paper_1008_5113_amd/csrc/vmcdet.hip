@@ -396,8 +396,8 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
     size_t o_llen = add(nn * 4), o_lcol = add(nn * F * 4), o_lval = add(nn * F * 8);
     size_t o_ulen = add(nn * 4), o_ucol = add(nn * F * 4), o_uval = add(nn * F * 8), o_udiag = add(nn * 8);
     size_t o_udinv = add(nn * 8), o_udinv32 = add(nn * 4);
-    size_t o_lp = add((nn + 1) * 4), o_lc = add(nn * F * 4), o_lv64 = add(nn * F * 8), o_lv32 = add(nn * F * 4);
-    size_t o_up = add((nn + 1) * 4), o_uc = add(nn * F * 4), o_uv64 = add(nn * F * 8), o_uv32 = add(nn * F * 4);
+    size_t o_lp = add((nn + 1) * 4), o_lc = add(nn * F * 2), o_lv64 = add(nn * F * 8), o_lv32 = add(nn * F * 4);
+    size_t o_up = add((nn + 1) * 4), o_uc = add(nn * F * 2), o_uv64 = add(nn * F * 8), o_uv32 = add(nn * F * 4);
     size_t o_q = add(nn * 4);
     size_t o_Z64 = p->precision == VMC_PREC_FP64 ? add((size_t)mm * nn * 8) : 0;
     size_t o_Z32 = p->precision == VMC_PREC_MIXED ? add((size_t)mm * nn * 4) : 0;
