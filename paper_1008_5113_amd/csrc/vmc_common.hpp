@@ -19,18 +19,27 @@ struct LdsLayout {
 
 __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// ILUTP: ILU_R rows are factored concurrently, one wave each, every wave with
+// a hashed sparse work row, a candidate table and its multipliers.
+constexpr int ILU_R = 3;
+constexpr int IW_HS = 1024;  // hash slots per wave (power of two)
+constexpr int IW_NZ = 512;   // work-row entries per wave
+constexpr int IW_C = 384;    // elimination candidates per row
+constexpr int IW_L = 192;    // multipliers per row before the fill limit
+
+__host__ __device__ inline size_t ilu_wave_bytes() {
+  return align_up((size_t)IW_HS * 4, 16) + align_up((size_t)IW_NZ * 2, 16) + (size_t)IW_NZ * 8 +
+         align_up((size_t)IW_C * 2, 16) * 3 + (size_t)IW_C * 8 + align_up((size_t)IW_L * 2, 16) +
+         (size_t)IW_L * 8;
+}
+
 __host__ __device__ inline size_t ilutp_lds_bytes(int n) {
   size_t b = 0;
-  b += align_up((size_t)n * 8, 16);              // wv: dense work row
-  b += align_up((size_t)(n + 31) / 32 * 4, 16);  // presence bitmap
-  b += align_up((size_t)n * 2, 16);              // pinv
-  b += align_up((size_t)n * 2, 16);              // q
-  b += align_up((size_t)NZMAX * 2, 16);          // work-row column list
-  b += align_up((size_t)LMAX * 2, 16);           // multiplier positions
-  b += align_up((size_t)LMAX * 8, 16);           // multiplier values
-  b += (size_t)ilu_cmax(n) * 8 + align_up((size_t)ilu_cmax(n) * 2, 16) * 3;  // candidate tables
-  b += align_up((size_t)SCAP * 2, 16);           // staged U-row columns
-  b += (size_t)SCAP * 8;                         // staged U-row values
+  b += align_up((size_t)n * 2, 16);  // pinv
+  b += align_up((size_t)n * 2, 16);  // q
+  const size_t waves = ILU_R * ilu_wave_bytes();
+  const size_t tmp = (size_t)n * 4;  // column relabelling after the factorisation
+  b += waves > tmp ? waves : tmp;
   return b;
 }
 

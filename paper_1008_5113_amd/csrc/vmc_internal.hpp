@@ -23,14 +23,7 @@ constexpr int NT = 512;        // threads per walker workgroup
 constexpr int NWAVE = NT / 64;
 constexpr int BLK = 64;        // rows per triangular-solve block (one lane per row)
 constexpr int MAXIT = 64;      // largest supported GMRES iteration count
-constexpr int NZMAX = 512;     // ILUTP work-row entry capacity
-constexpr int LMAX = 256;      // ILUTP multipliers per row before the fill limit
-constexpr int CMAX = 384;      // ILUTP elimination candidates per row (large n)
 
-// Candidate capacity: small systems can be nearly dense, large lattices are
-// bounded by the orbital stencil.
-__host__ __device__ inline int ilu_cmax(int n) { return n <= 1024 ? (n < 512 ? n : 512) : CMAX; }
-constexpr int SCAP = 880;      // ILUTP staged U-row entries per row
 constexpr int MMAX_CAP = 256;  // largest supported m_max
 
 // In-kernel phase timers (wall-clock ticks, accumulated by thread 0).

@@ -159,76 +159,88 @@ VMC_PHASE int ilutp_row_cap_extra(const Walker& W, const DevParams& P, Smem& S) 
   return (int)ceil(tot / (2.0 * W.n));
 }
 
-// Fetch the diagonal, length and (when it fits) the entries of U row k for
-// every candidate that has not been fetched yet, into the LDS staging area.
-// One batch of independent loads instead of one dependent load per candidate.
-struct IluCand {
-  short* pos;    // candidate position k (CAND_DONE once eliminated)
-  double* diag;  // u_kk
-  short* off;    // staging offset; -1 not fetched; -2 fetched but read from global
-  short* len;    // off-diagonal length of U row k
-  short* scol;   // staged columns (labels)
-  double* sval;  // staged values
+// Rows are factored concurrently by ILU_R waves (row i by wave i mod ILU_R),
+// each with its own sparse work row.  The row algorithm is exactly the serial
+// one; only the waiting differs:
+// - rows finish in order, and FIN (LDS) counts the finished rows.  Positions
+//   below FIN hold their final column labels, because a pivot of row j only
+//   swaps positions >= j;
+// - a row eliminates, in increasing order, the candidates whose positions are
+//   already final.  When it runs out, it waits for FIN to advance and scans
+//   the newly final positions for labels present in its work row;
+// - the drop, fill-limit and pivot decisions of row i run once all rows
+//   before i have finished, on the same data the serial algorithm would see.
+constexpr int CAND_DONE = 32767;
+constexpr int IC_FIN = 24;
+constexpr int IC_FAIL = 25;
+constexpr int SPIN_CAP = 1 << 22;  // bound on every wait; exceeding it is an error
+
+__device__ inline int lds_acquire(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ inline void lds_release(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// One wave's work row and candidate table.
+struct IluWave {
+  int* hent;      // hash: (label << 16) | slot, -1 empty
+  short* slab;    // slot -> label
+  double* sval;   // slot -> value
+  short* cpos;    // candidate position (CAND_DONE once eliminated)
+  short* clab;    // candidate label
+  short* clen;    // length of U row cpos
+  double* cdiag;  // u_kk of row cpos
+  short* lk;      // kept multipliers: positions
+  double* lv;     //                   values
 };
 
-constexpr int ST_UNFETCHED = -1;
-constexpr int CAND_DONE = 32767;
-constexpr int ST_GLOBAL = -2;
-constexpr int STAGE_UNR = 8;
+__device__ inline IluWave ilu_wave_carve(char* base) {
+  IluWave R;
+  R.hent = (int*)base;     base += align_up((size_t)IW_HS * 4, 16);
+  R.slab = (short*)base;   base += align_up((size_t)IW_NZ * 2, 16);
+  R.sval = (double*)base;  base += (size_t)IW_NZ * 8;
+  R.cpos = (short*)base;   base += align_up((size_t)IW_C * 2, 16);
+  R.clab = (short*)base;   base += align_up((size_t)IW_C * 2, 16);
+  R.clen = (short*)base;   base += align_up((size_t)IW_C * 2, 16);
+  R.cdiag = (double*)base; base += (size_t)IW_C * 8;
+  R.lk = (short*)base;     base += align_up((size_t)IW_L * 2, 16);
+  R.lv = (double*)base;
+  return R;
+}
 
-VMC_PHASE void ilu_fetch_pending(const Walker& W, IluCand& C, int ncand, int& stoff) {
-  const int lane = lane_id();
-  const int F = W.F;
-  for (int s0 = 0; s0 < ncand; s0 += 64) {
-    const int s = s0 + lane;
-    bool need = false;
-    int k = 0, len = 0;
-    if (s < ncand && C.off[s] == ST_UNFETCHED) {
-      need = true;
-      k = C.pos[s];
-      C.diag[s] = W.u_diag[k];
-      len = W.u_len[k];
-      C.len[s] = (short)len;
-    }
-    // exclusive prefix sum of the lengths of needed slots
-    int pre = need ? len : 0;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int t = __shfl_up(pre, o, 64);
-      if (lane >= o) pre += t;
-    }
-    const int total = __shfl(pre, 63, 64);
-    pre -= need ? len : 0;
-    int off = ST_GLOBAL;
-    if (need && stoff + pre + len <= SCAP) off = stoff + pre;
-    if (need) C.off[s] = (short)off;
-    const bool stage = need && off >= 0;
-    // copy the rows: each lane its own row, STAGE_UNR entries per pass
-    for (int base = 0;; base += STAGE_UNR) {
-      const bool more = stage && base < len;
-      if (!__ballot(more)) break;
-      int cc[STAGE_UNR];
-      double vv[STAGE_UNR];
-#pragma unroll
-      for (int t = 0; t < STAGE_UNR; ++t) {
-        const int e = base + t;
-        if (more && e < len) {
-          cc[t] = W.u_col[(size_t)k * F + e];
-          vv[t] = W.u_val[(size_t)k * F + e];
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < STAGE_UNR; ++t) {
-        const int e = base + t;
-        if (more && e < len) {
-          C.scol[off + e] = (short)cc[t];
-          C.sval[off + e] = vv[t];
-        }
-      }
-    }
-    if (stoff + total <= SCAP) stoff += total;
-    else stoff = SCAP;  // later fetches read from global
+__device__ inline int ilu_hash(int c) { return (int)(((unsigned)c * 2654435761u) >> 22); }
+
+// Slot of label c in the work row, or -1.
+__device__ inline int ilu_find(const int* hent, int c) {
+  int h = ilu_hash(c);
+  while (true) {
+    const int e = hent[h];
+    if (e == -1) return -1;
+    if ((e >> 16) == c) return e & 0xFFFF;
+    h = (h + 1) & (IW_HS - 1);
   }
+}
+
+__device__ inline void ilu_insert(int* hent, int c, int slot) {
+  int h = ilu_hash(c);
+  while (atomicCAS(&hent[h], -1, (c << 16) | slot) != -1) h = (h + 1) & (IW_HS - 1);
+}
+
+// Append the lanes flagged `add` as candidates (position p, label c), with
+// the diagonal and length of U row p.  Returns the new count.
+__device__ inline int ilu_add_cands(const Walker& W, IluWave& R, int ncand, bool add, int p, int c) {
+  const int lane = lane_id();
+  const unsigned long long mask = __ballot(add);
+  const int before = __popcll(mask & ((1ull << lane) - 1ull));
+  if (add && ncand + before < IW_C) {
+    const int s = ncand + before;
+    R.cpos[s] = (short)p;
+    R.clab[s] = (short)c;
+    R.cdiag[s] = W.u_diag[p];
+    R.clen[s] = (short)W.u_len[p];
+  }
+  return ncand + __popcll(mask);
 }
 
 VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
@@ -236,152 +248,162 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
   const int F = W.F;
   const int pfill = ilutp_row_cap_extra(W, P, S);
   char* base = S.A;
-  double* wv = (double*)base;               base += align_up((size_t)n * 8, 16);
-  unsigned* pbits = (unsigned*)base;        base += align_up((size_t)(n + 31) / 32 * 4, 16);
   short* pinv = (short*)base;               base += align_up((size_t)n * 2, 16);
   short* q = (short*)base;                  base += align_up((size_t)n * 2, 16);
-  short* nzc = (short*)base;                base += align_up((size_t)NZMAX * 2, 16);
-  short* lk = (short*)base;                 base += align_up((size_t)LMAX * 2, 16);
-  double* lv = (double*)base;               base += align_up((size_t)LMAX * 8, 16);
-  const int cmax = ilu_cmax(n);
-  IluCand C;
-  C.diag = (double*)base;                   base += (size_t)cmax * 8;
-  C.pos = (short*)base;                     base += align_up((size_t)cmax * 2, 16);
-  C.off = (short*)base;                     base += align_up((size_t)cmax * 2, 16);
-  C.len = (short*)base;                     base += align_up((size_t)cmax * 2, 16);
-  C.scol = (short*)base;                    base += align_up((size_t)SCAP * 2, 16);
-  C.sval = (double*)base;
+  const int wid = wave_id();
+  IluWave R = ilu_wave_carve(base + (size_t)(wid < ILU_R ? wid : 0) * ilu_wave_bytes());
 
   for (int k = vmc_tid(); k < n; k += NT) {
-    wv[k] = 0.0;
     pinv[k] = (short)k;
     q[k] = (short)k;
   }
-  for (int k = vmc_tid(); k < (n + 31) / 32; k += NT) pbits[k] = 0u;
+  if (wid < ILU_R)
+    for (int h = lane_id(); h < IW_HS; h += 64) R.hent[h] = -1;
+  if (vmc_tid() == 0) {
+    S.ic[IC_FIN] = 0;
+    S.ic[IC_FAIL] = 0;
+  }
   __syncthreads();
 
-  int status = WST_OK;
-  if (wave_id() == 0) {
+  if (wid < ILU_R) {
     const int lane = lane_id();
     const double droptol = P.droptol, permtol = P.permtol;
-    for (int i = 0; i < n && status == WST_OK; ++i) {
-      // 1. load row i; its entries left of the diagonal are the first candidates
+    int status = WST_OK;
+    for (int i = wid; i < n; i += ILU_R) {
+      if (lds_acquire(&S.ic[IC_FAIL])) break;
+      int known = min(lds_acquire(&S.ic[IC_FIN]), i);  // positions < known are final
+      // 1. load row i into the work row; entries at final positions left of
+      //    the diagonal are the first candidates
       const int len = W.a_len[i];
+      if (len > IW_NZ) { status = WST_CAPACITY; break; }
       double nrm = 0.0;
-      int nl0 = 0, nu0 = 0;
       int ncand = 0;
       for (int e0 = 0; e0 < len; e0 += 64) {
         const int e = e0 + lane;
         bool cand = false;
-        int k = 0;
+        int c = 0, k = 0;
         if (e < len) {
-          const int c = W.a_col[(size_t)i * W.W + e];
+          c = W.a_col[(size_t)i * W.W + e];
           const double v = W.a_val[(size_t)i * W.W + e];
-          wv[c] = v;
-          atomicOr(&pbits[c >> 5], 1u << (c & 31));
-          nzc[e] = (short)c;
+          R.slab[e] = (short)c;
+          R.sval[e] = v;
+          ilu_insert(R.hent, c, e);
           nrm += v * v;
           k = pinv[c];
-          nl0 += (k < i);
-          nu0 += (k > i);
-          cand = k < i;
+          cand = k < known;
         }
-        const unsigned long long mask = __ballot(cand);
-        const int before = __popcll(mask & ((1ull << lane) - 1ull));
-        if (cand && ncand + before < cmax) {
-          C.pos[ncand + before] = (short)k;
-          C.off[ncand + before] = ST_UNFETCHED;
-        }
-        ncand += __popcll(mask);
+        ncand = ilu_add_cands(W, R, ncand, cand, k, c);
       }
-      if (ncand > cmax) { status = WST_CAPACITY; break; }
+      if (ncand > IW_C) { status = WST_CAPACITY; break; }
       nrm = wave_sum(nrm);
-      nl0 = wave_sumi(nl0);
-      nu0 = wave_sumi(nu0);
       const double tau = droptol * sqrt(nrm);
       int nz = len;
       int lcount = 0;
-      int stoff = 0;
       // 2. eliminate in increasing position order
       while (true) {
         int best = CAND_DONE, bslot = -1;
         for (int s = lane; s < ncand; s += 64) {
-          const int p = C.pos[s];
+          const int p = R.cpos[s];
           if (p < best) { best = p; bslot = s; }
+        }
+        const int bmin = wave_mini(best);
+        if (bmin == CAND_DONE) {
+          if (known >= i) break;
+          // wait for more rows to finish, then scan the newly final positions
+          int f = known, spins = 0;
+          while (true) {
+            f = lds_acquire(&S.ic[IC_FIN]);
+            if (f > known) break;
+            if (lds_acquire(&S.ic[IC_FAIL]) || ++spins > SPIN_CAP) { status = WST_CAPACITY; break; }
+          }
+          if (status != WST_OK) break;
+          f = min(f, i);
+          for (int p0 = known; p0 < f; p0 += 64) {
+            const int p = p0 + lane;
+            bool add = false;
+            int c = 0;
+            if (p < f) {
+              c = q[p];
+              add = ilu_find(R.hent, c) >= 0;
+            }
+            ncand = ilu_add_cands(W, R, ncand, add, p, c);
+          }
+          if (ncand > IW_C) { status = WST_CAPACITY; break; }
+          known = f;
+          continue;
         }
         {
           // positions are distinct, so exactly one lane holds the minimum
-          const int bmin = wave_mini(best);
-          if (bmin == CAND_DONE) break;
           const unsigned long long who = __ballot(best == bmin);
           bslot = readlane_i(bslot, __ffsll((long long)who) - 1);
           best = bmin;
         }
-        if (C.off[bslot] == ST_UNFETCHED) ilu_fetch_pending(W, C, ncand, stoff);
-        const int c = q[best];
-        const double lik = wv[c] / C.diag[bslot];
-        if (lane == 0) C.pos[bslot] = (short)CAND_DONE;
+        const int sk = ilu_find(R.hent, R.clab[bslot]);
+        const double lik = R.sval[sk] / R.cdiag[bslot];
+        if (lane == 0) R.cpos[bslot] = (short)CAND_DONE;
         if (fabs(lik) < tau) continue;
-        if (lcount >= LMAX) { status = WST_CAPACITY; break; }
-        if (lane == 0) { lk[lcount] = (short)best; lv[lcount] = lik; }
+        if (lcount >= IW_L) { status = WST_CAPACITY; break; }
+        if (lane == 0) { R.lk[lcount] = (short)best; R.lv[lcount] = lik; }
         ++lcount;
-        const int ul = C.len[bslot];
-        const int uoff = C.off[bslot];
+        const int ul = R.clen[bslot];
         for (int e0 = 0; e0 < ul; e0 += 64) {
           const int e = e0 + lane;
-          bool isnew = false, newcand = false;
+          bool isnew = false, cand = false;
           int c2 = 0, k2 = 0;
           double v2 = 0.0;
           if (e < ul) {
-            if (uoff >= 0) {
-              c2 = C.scol[uoff + e];
-              v2 = C.sval[uoff + e];
-            } else {
-              c2 = W.u_col[(size_t)best * F + e];
-              v2 = W.u_val[(size_t)best * F + e];
-            }
-            const unsigned bit = 1u << (c2 & 31);
-            const unsigned old = atomicOr(&pbits[c2 >> 5], bit);
-            if (old & bit) {
-              wv[c2] -= lik * v2;
-            } else {
-              wv[c2] = -lik * v2;
-              isnew = true;
-              k2 = pinv[c2];
-              newcand = k2 < i;
-            }
+            c2 = W.u_col[(size_t)best * F + e];
+            v2 = W.u_val[(size_t)best * F + e];
+            // the columns of one U row are distinct: no two lanes share a label
+            const int s2 = ilu_find(R.hent, c2);
+            if (s2 >= 0) R.sval[s2] -= lik * v2;
+            else isnew = true;
           }
-          unsigned long long mask = __ballot(isnew);
-          int before = __popcll(mask & ((1ull << lane) - 1ull));
-          if (isnew && nz + before < NZMAX) nzc[nz + before] = (short)c2;
+          const unsigned long long mask = __ballot(isnew);
+          const int before = __popcll(mask & ((1ull << lane) - 1ull));
+          if (isnew && nz + before < IW_NZ) {
+            const int s2 = nz + before;
+            R.slab[s2] = (short)c2;
+            R.sval[s2] = -lik * v2;
+            ilu_insert(R.hent, c2, s2);
+            k2 = pinv[c2];
+            cand = k2 < known;
+          }
           nz += __popcll(mask);
-          mask = __ballot(newcand);
-          before = __popcll(mask & ((1ull << lane) - 1ull));
-          if (newcand && ncand + before < cmax) {
-            C.pos[ncand + before] = (short)k2;
-            C.off[ncand + before] = ST_UNFETCHED;
-          }
-          ncand += __popcll(mask);
+          if (nz > IW_NZ) break;
+          ncand = ilu_add_cands(W, R, ncand, cand, k2, c2);
         }
-        if (nz > NZMAX || ncand > cmax) { status = WST_CAPACITY; break; }
+        if (nz > IW_NZ || ncand > IW_C) { status = WST_CAPACITY; break; }
       }
       if (status != WST_OK) break;
 
-      // 3./4. U part: threshold drop (never the current diagonal column), fill limit
+      // 3. U part (rows < i have all finished: positions are final).  Drop
+      //    below tau (never the current diagonal column), keep the nU0 + p
+      //    largest, where nU0/nL0 count the row's original entries right/left
+      //    of the diagonal.
+      int nl0 = 0, nu0 = 0;
+      for (int e = lane; e < len; e += 64) {
+        const int k = pinv[R.slab[e]];
+        nl0 += (k < i);
+        nu0 += (k > i);
+      }
+      nl0 = wave_sumi(nl0);
+      nu0 = wave_sumi(nu0);
       const int cd = q[i];
-      const bool cd_present = (pbits[cd >> 5] >> (cd & 31)) & 1u;
+      const int sd = ilu_find(R.hent, cd);
+      const bool cd_present = sd >= 0;
       const int ucap = nu0 + pfill;
       const int lcap = nl0 + pfill;
       int ucnt = 0;
       for (int e = lane; e < nz; e += 64) {
-        const int c = nzc[e];
-        if (c != cd && pinv[c] >= i && fabs(wv[c]) >= tau) ++ucnt;
+        const int c = R.slab[e];
+        if (c != cd && pinv[c] >= i && fabs(R.sval[e]) >= tau) ++ucnt;
       }
       ucnt = wave_sumi(ucnt);
-      double vmax = -1.0;
+      double vmax = -1.0, vmaxv = 0.0;
       int cmax_pos = 0x7fffffff;
-      const double vd = cd_present ? wv[cd] : 0.0;
-      if (cd_present) { vmax = fabs(vd); cmax_pos = i; }
+      const double vd = cd_present ? R.sval[sd] : 0.0;
+      if (cd_present) { vmax = fabs(vd); vmaxv = vd; cmax_pos = i; }
       int uwrite = 0;
       int* out_col = W.u_col + (size_t)i * F;
       double* out_val = W.u_val + (size_t)i * F;
@@ -391,8 +413,8 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
         int c = 0;
         double v = 0.0;
         if (e < nz) {
-          c = nzc[e];
-          v = wv[c];
+          c = R.slab[e];
+          v = R.sval[e];
           if (c != cd && pinv[c] >= i && fabs(v) >= tau) {
             keep = true;
             if (ucnt > ucap) {
@@ -400,9 +422,9 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
               const int kp = pinv[c];
               int rank = 0;
               for (int f = 0; f < nz; ++f) {
-                const int c3 = nzc[f];
+                const int c3 = R.slab[f];
                 if (c3 == cd || pinv[c3] < i) continue;
-                const double a3 = fabs(wv[c3]);
+                const double a3 = fabs(R.sval[f]);
                 if (a3 < tau) continue;
                 if (a3 > av || (a3 == av && pinv[c3] < kp)) ++rank;
               }
@@ -410,30 +432,31 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
             }
           }
         }
-        unsigned long long mask = __ballot(keep);
+        const unsigned long long mask = __ballot(keep);
         const int before = __popcll(mask & ((1ull << lane) - 1ull));
         if (keep) {
           const int o = uwrite + before;
           if (o < F) { out_col[o] = c; out_val[o] = v; }
           const double av = fabs(v);
           const int kp = pinv[c];
-          if (av > vmax || (av == vmax && kp < cmax_pos)) { vmax = av; cmax_pos = kp; }
+          if (av > vmax || (av == vmax && kp < cmax_pos)) { vmax = av; vmaxv = v; cmax_pos = kp; }
         }
         uwrite += __popcll(mask);
       }
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
         const double ov = __shfl_xor(vmax, o, 64);
+        const double ovv = __shfl_xor(vmaxv, o, 64);
         const int op = __shfl_xor(cmax_pos, o, 64);
-        if (ov > vmax || (ov == vmax && op < cmax_pos)) { vmax = ov; cmax_pos = op; }
+        if (ov > vmax || (ov == vmax && op < cmax_pos)) { vmax = ov; vmaxv = ovv; cmax_pos = op; }
       }
       if (uwrite > F - 1) { status = WST_CAPACITY; break; }
       if (!(vmax > 0.0)) { status = WST_SINGULAR; break; }
-      // 5. pivot: swap the diagonal column with the largest entry's column
+      // 4. pivot: swap the diagonal column with the largest entry's column
       double dval = vd;
       if (permtol * vmax > fabs(vd) && cmax_pos != i) {
         const int cm = q[cmax_pos];
-        dval = wv[cm];
+        dval = vmaxv;
         if (lane == 0) {
           q[i] = (short)cm;
           q[cmax_pos] = (short)cd;
@@ -457,7 +480,7 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
         }
       }
       if (dval == 0.0) { status = WST_SINGULAR; break; }
-      // 4. L part: keep the lcap largest multipliers
+      // 5. L part: keep the lcap largest multipliers
       int lwrite = 0;
       int* lcol = W.l_col + (size_t)i * F;
       double* lval = W.l_val + (size_t)i * F;
@@ -467,21 +490,21 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
         if (e < lcount) {
           keep = true;
           if (lcount > lcap) {
-            const double av = fabs(lv[e]);
-            const int kp = lk[e];
+            const double av = fabs(R.lv[e]);
+            const int kp = R.lk[e];
             int rank = 0;
             for (int f = 0; f < lcount; ++f) {
-              const double a3 = fabs(lv[f]);
-              if (a3 > av || (a3 == av && lk[f] < kp)) ++rank;
+              const double a3 = fabs(R.lv[f]);
+              if (a3 > av || (a3 == av && R.lk[f] < kp)) ++rank;
             }
             keep = rank < lcap;
           }
         }
-        unsigned long long mask = __ballot(keep);
+        const unsigned long long mask = __ballot(keep);
         const int before = __popcll(mask & ((1ull << lane) - 1ull));
         if (keep) {
           const int o = lwrite + before;
-          if (o < F) { lcol[o] = lk[e]; lval[o] = lv[e]; }
+          if (o < F) { lcol[o] = R.lk[e]; lval[o] = R.lv[e]; }
         }
         lwrite += __popcll(mask);
       }
@@ -491,19 +514,15 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
         W.u_diag[i] = dval;
         W.l_len[i] = lwrite;
       }
-      // 6. clear the work row
-      for (int e = lane; e < nz; e += 64) {
-        const int c = nzc[e];
-        wv[c] = 0.0;
-        pbits[c >> 5] = 0u;
-      }
+      // 6. clear the work row, then publish row i as finished
+      for (int h = lane; h < IW_HS; h += 64) R.hent[h] = -1;
       __threadfence_block();
+      if (lane == 0) lds_release(&S.ic[IC_FIN], i + 1);
     }
+    if (status != WST_OK && lane == 0) atomicOr(&S.ic[IC_FAIL], status);
   }
   __syncthreads();
-  if (vmc_tid() == 0) S.ic[1] = status;
-  __syncthreads();
-  status = S.ic[1];
+  const int status = S.ic[IC_FAIL];
   __syncthreads();
   if (status != WST_OK) return status;
 
@@ -526,7 +545,7 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
   wg_pack_factors(W, S);
   // colsite_new[k] = colsite_old[q[k]]; cpos[s] = pinv[cpos[s]]
   __syncthreads();
-  int* tmp = (int*)wv;  // reuse the work row (n ints fit in n doubles)
+  int* tmp = (int*)base;  // the work rows' bytes (they hold at least n ints)
   for (int k = vmc_tid(); k < n; k += NT) tmp[k] = W.colsite[q[k]];
   __syncthreads();
   for (int k = vmc_tid(); k < n; k += NT) {
