@@ -21,11 +21,11 @@ __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a -
 
 // ILUTP: ILU_R rows are factored concurrently, one wave each, every wave with
 // a hashed sparse work row, a candidate table and its multipliers.
-constexpr int ILU_R = 3;
+constexpr int ILU_R = 4;
 constexpr int IW_HS = 1024;  // hash slots per wave (power of two)
 constexpr int IW_NZ = 512;   // work-row entries per wave
-constexpr int IW_C = 384;    // elimination candidates per row
-constexpr int IW_L = 192;    // multipliers per row before the fill limit
+constexpr int IW_C = 192;    // elimination candidates per row
+constexpr int IW_L = 160;    // multipliers per row before the fill limit
 
 __host__ __device__ inline size_t ilu_wave_bytes() {
   return align_up((size_t)IW_HS * 4, 16) + align_up((size_t)IW_NZ * 2, 16) + (size_t)IW_NZ * 8 +

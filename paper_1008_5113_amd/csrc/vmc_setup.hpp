@@ -227,11 +227,43 @@ __device__ inline void ilu_insert(int* hent, int c, int slot) {
   while (atomicCAS(&hent[h], -1, (c << 16) | slot) != -1) h = (h + 1) & (IW_HS - 1);
 }
 
+// Drop the eliminated candidates from the table (their order is irrelevant:
+// the next candidate is always the smallest position).
+__device__ inline int ilu_compact(IluWave& R, int ncand) {
+  const int lane = lane_id();
+  int w = 0;
+  for (int s0 = 0; s0 < ncand; s0 += 64) {
+    const int s = s0 + lane;
+    int p = CAND_DONE, c = 0, l = 0;
+    double d = 0.0;
+    if (s < ncand) {
+      p = R.cpos[s];
+      c = R.clab[s];
+      l = R.clen[s];
+      d = R.cdiag[s];
+    }
+    const bool live = p != CAND_DONE;
+    const unsigned long long mask = __ballot(live);
+    const int before = __popcll(mask & ((1ull << lane) - 1ull));
+    if (live) {
+      const int t = w + before;
+      R.cpos[t] = (short)p;
+      R.clab[t] = (short)c;
+      R.clen[t] = (short)l;
+      R.cdiag[t] = d;
+    }
+    w += __popcll(mask);
+  }
+  return w;
+}
+
 // Append the lanes flagged `add` as candidates (position p, label c), with
-// the diagonal and length of U row p.  Returns the new count.
+// the diagonal and length of U row p.  Returns the new count; a count above
+// IW_C means the table overflowed.
 __device__ inline int ilu_add_cands(const Walker& W, IluWave& R, int ncand, bool add, int p, int c) {
   const int lane = lane_id();
   const unsigned long long mask = __ballot(add);
+  if (ncand + __popcll(mask) > IW_C) ncand = ilu_compact(R, ncand);
   const int before = __popcll(mask & ((1ull << lane) - 1ull));
   if (add && ncand + before < IW_C) {
     const int s = ncand + before;

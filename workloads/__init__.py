@@ -194,7 +194,7 @@ def mixed_n4000(n_walkers: int = 512) -> Instance:
     ws = [Walker(0, initial_positions(s.sites, s.box, w, 0.3), w) for w in range(n_walkers)]
     # m_max: the refactor period balancing the measured ILUTP cost against the
     # growing cost of applying the stored updates
-    return Instance("mixed_n4000", [s], ws, Params(step=0.25, sweeps=30, mixed=True, m_max=128))
+    return Instance("mixed_n4000", [s], ws, Params(step=0.25, sweeps=30, mixed=True, m_max=96))
 
 
 def stress_n8192(n_walkers: int = 64) -> Instance:
