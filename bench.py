@@ -35,11 +35,12 @@ def log(msg: str):
 
 
 # ---------------------------------------------------------------------------
-# Algorithmic bytes of the method per timed region:
-# every GMRES iteration streams A, L and U once (values + 4-byte indices), the
-# stored update vectors once, and a handful of n-vectors; a mixed-precision
+# Algorithmic bytes of the method per timed region: every GMRES iteration
+# streams A, L and U once (values + 2-byte column positions), the stored
+# update vectors once, and a handful of n-vectors; a mixed-precision
 # refinement pass streams A in FP64 once.
 # ---------------------------------------------------------------------------
+IDX = 2  # bytes per stored column position
 def algorithmic_bytes(stats0, stats1, nnz, n, mixed: bool):
     sv = 4 if mixed else 8
     nA, nL, nU = nnz
@@ -51,11 +52,11 @@ def algorithmic_bytes(stats0, stats1, nnz, n, mixed: bool):
         passes = b["refine_passes"] - a["refine_passes"]
         msum = b["update_sum"] - a["update_sum"]
         m_avg = msum / inner if inner else 0.0
-        per_iter = (nA + nL + nU) * (sv + 4) + n * sv * (1 + m_avg) + 4 * n * sv
+        per_iter = (nA + nL + nU) * (sv + IDX) + n * sv * (1 + m_avg) + 4 * n * sv
         tot += iters * per_iter
         tot += inner * (n * 8)                   # solution accumulation write
         if mixed:
-            tot += (solves + passes) * (nA * (8 + 4) + n * 16)
+            tot += (solves + passes) * (nA * (8 + IDX) + n * 16)
     return tot
 
 
@@ -199,11 +200,11 @@ def phase_bench(inst, precision, walkers, stream_ptr, reps, warm_steps, **kw):
     nA, nL, nU = nnz
     sv = 4 if precision == vm.PREC_MIXED else 8
     per_rep = {
-        "spmv": nA * (sv + 4) + n * (4 + sv),
-        "lsolve": (nL) * (sv + 4) + n * 4,
-        "usolve": (nU - n) * (sv + 4) + n * (4 + sv),
+        "spmv": nA * (sv + IDX) + n * (4 + sv),
+        "lsolve": (nL) * (sv + IDX) + n * 4,
+        "usolve": (nU - n) * (sv + IDX) + n * (4 + sv),
         "updates": m_avg * n * sv,
-        "resid64": nA * 12 + n * (4 + 8 + 8),
+        "resid64": nA * (8 + IDX) + n * (4 + 8 + 8),
     }
     out = {"m_avg": m_avg, "nnz_per_row": (nnz / n).tolist()}
     stream = torch.cuda.current_stream()

@@ -349,8 +349,9 @@ __device__ inline int wrap_index(int i, int L) {
 // Entries are written in candidate order to out_col/out_val (global) as column
 // positions cmap[site].  Returns the entry count (may exceed cap; entries past
 // cap are not written).
+template <typename CT>
 __device__ inline int wave_row(const Walker& W, double rx, double ry, double rz, const int* cmap,
-                               int* out_col, double* out_val, float* out_val32, int cap) {
+                               CT* out_col, double* out_val, float* out_val32, int cap) {
   const int lane = lane_id();
   const double R = W.cutoff + W.margin;
   int lox, cx, loy, cy, loz, cz;
@@ -385,7 +386,7 @@ __device__ inline int wave_row(const Walker& W, double rx, double ry, double rz,
     if (hit) {
       int o = count + before;
       if (o < cap) {
-        out_col[o] = cmap[site];
+        out_col[o] = (CT)cmap[site];
         out_val[o] = val;
         if (out_val32) out_val32[o] = (float)val;
       }

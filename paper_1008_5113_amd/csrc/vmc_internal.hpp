@@ -82,7 +82,7 @@ struct Walker {
 
   // Slater matrix
   int GAS* a_len;
-  int GAS* a_col;
+  unsigned short GAS* a_col;
   double GAS* a_val;
   float GAS* a_val32;
 

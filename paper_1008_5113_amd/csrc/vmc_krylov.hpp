@@ -287,10 +287,9 @@ VMC_PHASE void wg_precond(const Walker& W, int m, int mmax, const KT* vin, int u
 }
 
 // Sparse row dot products for the SpMV: 8 threads per row, each thread owning
-// a contiguous chunk of SPMV_CH entries read with 16-byte loads (row starts
-// are 16-byte aligned because the row capacity is a multiple of 4); entries
-// past 8*SPMV_CH fall to a strided tail loop.  Rows shorter than the chunk
-// origin issue no loads, so the bytes read follow the row lengths.
+// a contiguous chunk of SPMV_CH entries: 16-bit columns read 4 at a time
+// (8-byte loads), values with 16-byte loads (rows are 64-byte aligned because
+// the row capacity is a multiple of 16).
 constexpr int SPMV_CH = 12;
 
 template <typename VT>
@@ -307,51 +306,76 @@ VMC_PHASE void load_vals4<double>(const double* p, double* v) {
   v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
 }
 
-// acc = sum over the thread's chunk of row (ac, av, len) of av[e] * x[ac[e]]
+// One thread's chunk of a row of A: SPMV_CH column positions (16-bit, packed
+// two per word) and values.  The loads are unconditional, so both rows of a
+// pass are in flight before the first one is consumed; entries at or past the
+// row length are masked at the use.
+template <typename VT>
+struct RowSeg {
+  uint2 c[SPMV_CH / 4];
+  VT v[SPMV_CH];
+};
+
+template <typename VT>
+VMC_PHASE void load_row_seg(RowSeg<VT>& g, const unsigned short* ac, const VT* av, int len, int Wc,
+                            int sub) {
+  const int e0 = sub * SPMV_CH;
+#pragma unroll
+  for (int p = 0; p < SPMV_CH / 4; ++p) {
+    const int e = e0 + 4 * p;
+    // groups past the row length re-read the row start (a line the first
+    // thread reads anyway), so the bytes fetched follow the row lengths
+    const int o = (e < len && e + 4 <= Wc) ? e : 0;
+    g.c[p] = *reinterpret_cast<const uint2*>(ac + o);
+    load_vals4<VT>(av + o, g.v + 4 * p);
+  }
+}
+
+// acc = sum over the thread's chunk of av[e] * x[ac[e]], e < len
 template <typename VT, typename XT, typename AT>
-VMC_PHASE AT row_chunk_dot(const int* ac, const VT* av, int len, int sub, const XT* x) {
+VMC_PHASE AT row_seg_dot(const RowSeg<VT>& g, int len, int sub, const XT* x) {
   const int e0 = sub * SPMV_CH;
   AT acc = 0;
-  if (e0 < len) {
-    int c[SPMV_CH];
-    VT v[SPMV_CH];
 #pragma unroll
-    for (int p = 0; p < SPMV_CH / 4; ++p) {
-      if (e0 + 4 * p < len) {
-        const int4 t = *reinterpret_cast<const int4*>(ac + e0 + 4 * p);
-        c[4 * p] = t.x; c[4 * p + 1] = t.y; c[4 * p + 2] = t.z; c[4 * p + 3] = t.w;
-        load_vals4<VT>(av + e0 + 4 * p, v + 4 * p);
-      } else {
+  for (int p = 0; p < SPMV_CH / 4; ++p) {
+    const unsigned lo = g.c[p].x, hi = g.c[p].y;
+    const int cc[4] = {(int)(lo & 0xFFFFu), (int)(lo >> 16), (int)(hi & 0xFFFFu), (int)(hi >> 16)};
 #pragma unroll
-        for (int k = 0; k < 4; ++k) { c[4 * p + k] = 0; v[4 * p + k] = 0; }
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < SPMV_CH; ++t)
-      if (e0 + t < len) acc += (AT)v[t] * (AT)x[c[t]];
+    for (int k = 0; k < 4; ++k)
+      if (e0 + 4 * p + k < len) acc += (AT)g.v[4 * p + k] * (AT)x[cc[k]];
   }
-  for (int e = 8 * SPMV_CH + sub; e < len; e += 8) acc += (AT)av[e] * (AT)x[ac[e]];
   return acc;
 }
 
-// w = A x (x in LDS or global), two rows per thread group per pass, row
-// lengths loaded one pass ahead.  When out_resid is set, writes e_unit - A x
+// w = A x (x in LDS or global), two rows per thread group per pass: both rows'
+// chunks are loaded before either is used, and the row lengths one pass
+// ahead.  Entries past 8*SPMV_CH (rows longer than the chunks cover) are
+// added by a strided tail loop.  When `resid` is set, writes e_unit - A x
 // instead and returns the partial sum of squares.
 template <typename VT, typename XT, typename AT, typename OT>
 VMC_PHASE double wg_rows_apply(const Walker& W, const VT* aval, const XT* x, OT* out, int unit,
-                                       bool resid) {
+                               bool resid) {
   const int n = W.n, Wc = W.W;
   const int rr = vmc_tid() >> 3, sub = vmc_tid() & 7;
   double sq = 0.0;
-  int l0 = (rr < n) ? W.a_len[rr] : 0;
-  int l1 = (rr + BLK < n) ? W.a_len[rr + BLK] : 0;
+  auto clamp_row = [&](int r) { return r < n ? r : 0; };
+  int l0 = W.a_len[clamp_row(rr)];
+  int l1 = W.a_len[clamp_row(rr + BLK)];
   for (int base = 0; base < n; base += 2 * BLK) {
     const int r0 = base + rr, r1 = r0 + BLK;
-    const int len0 = l0, len1 = l1;
-    l0 = (r0 + 2 * BLK < n) ? W.a_len[r0 + 2 * BLK] : 0;
-    l1 = (r1 + 2 * BLK < n) ? W.a_len[r1 + 2 * BLK] : 0;
-    AT a0 = (r0 < n) ? row_chunk_dot<VT, XT, AT>(W.a_col + (size_t)r0 * Wc, aval + (size_t)r0 * Wc, len0, sub, x) : (AT)0;
-    AT a1 = (r1 < n) ? row_chunk_dot<VT, XT, AT>(W.a_col + (size_t)r1 * Wc, aval + (size_t)r1 * Wc, len1, sub, x) : (AT)0;
+    const int len0 = r0 < n ? l0 : 0, len1 = r1 < n ? l1 : 0;
+    RowSeg<VT> g0, g1;
+    const size_t o0 = (size_t)clamp_row(r0) * Wc, o1 = (size_t)clamp_row(r1) * Wc;
+    load_row_seg<VT>(g0, W.a_col + o0, aval + o0, len0, Wc, sub);
+    load_row_seg<VT>(g1, W.a_col + o1, aval + o1, len1, Wc, sub);
+    l0 = W.a_len[clamp_row(r0 + 2 * BLK)];
+    l1 = W.a_len[clamp_row(r1 + 2 * BLK)];
+    AT a0 = row_seg_dot<VT, XT, AT>(g0, len0, sub, x);
+    AT a1 = row_seg_dot<VT, XT, AT>(g1, len1, sub, x);
+    if (len0 > 8 * SPMV_CH || len1 > 8 * SPMV_CH) {
+      for (int e = 8 * SPMV_CH + sub; e < len0; e += 8) a0 += (AT)aval[o0 + e] * (AT)x[W.a_col[o0 + e]];
+      for (int e = 8 * SPMV_CH + sub; e < len1; e += 8) a1 += (AT)aval[o1 + e] * (AT)x[W.a_col[o1 + e]];
+    }
     a0 = sum8(a0);
     a1 = sum8(a1);
     if (sub == 0) {

@@ -568,8 +568,8 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
     W.u_dinv32[i] = (float)dinv;
     for (int e = 0; e < ul; ++e) uc[e] = pinv[uc[e]];
     const int al = W.a_len[i];
-    int* ac = W.a_col + (size_t)i * W.W;
-    for (int e = 0; e < al; ++e) ac[e] = pinv[ac[e]];
+    unsigned short* ac = W.a_col + (size_t)i * W.W;
+    for (int e = 0; e < al; ++e) ac[e] = (unsigned short)pinv[ac[e]];
     W.ilu_q[i] = q[i];
   }
   __threadfence_block();

@@ -306,7 +306,7 @@ VMC_PHASE void wg_accept(const Walker& W, WalkerState* ws, const DevParams& P, S
   if (accept) {
     flags |= VMC_FLAG_ACCEPTED;
     for (int e = vmc_tid(); e < newlen; e += NT) {
-      W.a_col[(size_t)i * W.W + e] = W.new_col[e];
+      W.a_col[(size_t)i * W.W + e] = (unsigned short)W.new_col[e];
       const double v = W.new_val[e];
       W.a_val[(size_t)i * W.W + e] = v;
       W.a_val32[(size_t)i * W.W + e] = (float)v;
