@@ -158,8 +158,11 @@ VMC_PHASE void wg_trisolve_rows(const Walker& W, const int* ptr, const unsigned 
     }
     __syncthreads();
     if (wave_id() == 0) {
+      // the chain is the block's critical path: let this wave issue first
+      __builtin_amdgcn_s_setprio(3);
       KT a = st[lane_id()];
       a = block_chain<KT, FORWARD>(a, D);
+      __builtin_amdgcn_s_setprio(0);
       if (r0 + lane_id() < n) xs[r0 + lane_id()] = a;
     }
     __syncthreads();
