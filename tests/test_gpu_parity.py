@@ -286,8 +286,8 @@ def test_full_size_uneven_batch(vm):
 
 
 def test_full_size_stress_n8192(vm):
-    """16x16x32 jittered lattice with lognormal widths, 64 walkers, 120 steps
+    """16x16x32 jittered lattice with lognormal widths, 64 walkers, 60 steps
     (mixed precision); walker 0 replayed."""
     _say("case: full size stress n=8192 x 64 walkers")
     inst = wl.stress_n8192()
-    _full_config(vm, inst, 120, (0,))
+    _full_config(vm, inst, 60, (0,))
