@@ -49,7 +49,7 @@ __host__ __device__ inline size_t ilutp_lds_bytes(int n) {
 // (reduction slots and broadcast scalars) is live in every phase.
 __host__ __device__ inline LdsLayout lds_layout(int n, int ktb, int maxit, int mmax) {
   LdsLayout L;
-  size_t o = align_up((size_t)n, 4) * ktb + (size_t)BLK * BLK * ktb;  // xs, D
+  size_t o = align_up((size_t)n, 4) * ktb + align_up((size_t)DTILE * ktb, 16);  // xs, D
   L.hb = o; o += (MAXIT + 2) * 8;
   L.cs = o; o += (MAXIT + 1) * 8;
   L.sn = o; o += (MAXIT + 1) * 8;

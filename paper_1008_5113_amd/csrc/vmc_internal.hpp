@@ -22,6 +22,11 @@ namespace vmc {
 constexpr int NT = 512;        // threads per walker workgroup
 constexpr int NWAVE = NT / 64;
 constexpr int BLK = 64;        // rows per triangular-solve block (one lane per row)
+// In-block coefficient tile of the triangular solves: column-major with a
+// column stride of BLK + 1 (the 8 threads of a row scatter into 8 different
+// banks), plus one spare row that masked-off scatters write to.
+constexpr int DSTR = BLK + 1;
+constexpr int DTILE = BLK * DSTR + BLK;
 constexpr int MAXIT = 64;      // largest supported GMRES iteration count
 
 constexpr int MMAX_CAP = 256;  // largest supported m_max

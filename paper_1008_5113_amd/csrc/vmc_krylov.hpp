@@ -38,7 +38,7 @@ VMC_PHASE KT block_chain(KT a, const KT* D) {
 #pragma unroll
   for (int j = 0; j < B; ++j) {
     const int k = FORWARD ? j : BLK - 1 - j;
-    d0[j] = D[k * BLK + lane];
+    d0[j] = D[k * DSTR + lane];
   }
 #pragma unroll
   for (int q = 0; q < BLK / B; ++q) {
@@ -46,7 +46,7 @@ VMC_PHASE KT block_chain(KT a, const KT* D) {
 #pragma unroll
       for (int j = 0; j < B; ++j) {
         const int k = FORWARD ? B * (q + 1) + j : BLK - 1 - (B * (q + 1) + j);
-        d1[j] = D[k * BLK + lane];
+        d1[j] = D[k * DSTR + lane];
       }
     }
 #pragma unroll
@@ -93,18 +93,27 @@ VMC_PHASE void wg_trisolve_rows(const Walker& W, const int* ptr, const unsigned 
   const int rr = vmc_tid() >> 3, sub = vmc_tid() & 7;
   const int nb = (n + BLK - 1) / BLK;
   auto row_of = [&](int t) { return (t >= 0 && t < nb) ? (FORWARD ? t : nb - 1 - t) * BLK + rr : -1; };
-  int pa = 0, pb = 0, pok = 0;  // row pointers of the next block to load
-  auto load_ptr = [&](int t) {
-    const int r = row_of(t);
-    pok = (r >= 0 && r < n);
-    const int rc = pok ? r : 0;
-    pa = ptr[rc];
-    pb = ptr[rc + 1];
+  // Row pointers travel in three register sets with fixed roles: block t
+  // loads the pointers of block t+3 before it loads the rows of block t+2
+  // (whose pointers block t-1 loaded), so a pointer load is always older
+  // than the row loads issued after it and waiting for it leaves those in
+  // flight.
+  struct RowPtr {
+    int a, b, ok;
   };
-  auto load_chunk = [&](RowChunk<KT>& ch, int t) {
+  auto load_ptr = [&](RowPtr& P, int t) {
     const int r = row_of(t);
+    P.ok = (r >= 0 && r < n);
+    const int rc = P.ok ? r : 0;
+    P.a = ptr[rc];
+    P.b = ptr[rc + 1];
+  };
+  auto load_chunk = [&](RowChunk<KT>& ch, const RowPtr& P, int t) {
+    const int r = row_of(t);
+    const int pa = P.a;
+    const bool pok = P.ok;
     ch.ok = pok;
-    ch.len = pok ? pb - pa : 0;
+    ch.len = pok ? P.b - pa : 0;
     ch.start = pa;
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
@@ -115,7 +124,7 @@ VMC_PHASE void wg_trisolve_rows(const Walker& W, const int* ptr, const unsigned 
     }
     if (aux) ch.aux = aux[pok ? r : 0];
   };
-  auto block = [&](int t, const RowChunk<KT>& cur, RowChunk<KT>& ahead) {
+  auto block = [&](int t, const RowChunk<KT>& cur, RowChunk<KT>& ahead, RowPtr& pnew, const RowPtr& pold) {
     const bool live = t < nb;  // the padding blocks only issue loads
     const int r0 = (FORWARD ? t : nb - 1 - t) * BLK;
     const int r = r0 + rr;
@@ -123,31 +132,39 @@ VMC_PHASE void wg_trisolve_rows(const Walker& W, const int* ptr, const unsigned 
     int dpos[PF];
     const bool tail = cur.len > 8 * PF;
     if (live) {
+      // branch-free: every entry issues one gather (far entries; others read
+      // xs[0], whose value is discarded by a select: it may hold anything) and
+      // one tile write (in-block entries; others hit the spare row), so all of
+      // a thread's LDS accesses are in flight at once
+      int gi[PF];
+      bool gf[PF];
 #pragma unroll
       for (int k = 0; k < PF; ++k) {
         const int e = sub + 8 * k;
-        dpos[k] = -1;
-        if (e < cur.len) {
-          const int c = cur.col[k];
-          if (is_far(FORWARD, c, r0)) {
-            acc += cur.val[k] * xs[c];
-          } else {
-            dpos[k] = (c - r0) * BLK + rr;
-            D[dpos[k]] = cur.val[k];
-          }
-        }
+        const int c = cur.col[k];
+        const bool valid = e < cur.len;
+        const bool far = is_far(FORWARD, c, r0);
+        gf[k] = valid && far;
+        gi[k] = gf[k] ? c : 0;
+        dpos[k] = (valid && !far) ? (c - r0) * DSTR + rr : BLK * DSTR + lane_id();
+        D[dpos[k]] = cur.val[k];
+      }
+#pragma unroll
+      for (int k = 0; k < PF; ++k) {
+        const KT xk = xs[gi[k]];
+        acc += gf[k] ? cur.val[k] * xk : (KT)0;
       }
       if (tail) {
         for (int e = sub + 8 * PF; e < cur.len; e += 8) {
           const int c = cols[cur.start + e];
           const KT v = vals[cur.start + e];
           if (is_far(FORWARD, c, r0)) acc += v * xs[c];
-          else D[(c - r0) * BLK + rr] = v;
+          else D[(c - r0) * DSTR + rr] = v;
         }
       }
     }
-    load_chunk(ahead, t + 2);
-    load_ptr(t + 3);
+    load_ptr(pnew, t + 3);
+    load_chunk(ahead, pold, t + 2);
     if (!live) return;
     acc = sum8(acc);
     if (sub == 0) {
@@ -168,24 +185,26 @@ VMC_PHASE void wg_trisolve_rows(const Walker& W, const int* ptr, const unsigned 
     __syncthreads();
     if (tail) {
       // clear the row's whole tile row instead of re-reading its columns
-      for (int cc = sub; cc < BLK; cc += 8) D[cc * BLK + rr] = (KT)0;
+      for (int cc = sub; cc < BLK; cc += 8) D[cc * DSTR + rr] = (KT)0;
     } else {
 #pragma unroll
-      for (int k = 0; k < PF; ++k)
-        if (dpos[k] >= 0) D[dpos[k]] = (KT)0;
+      for (int k = 0; k < PF; ++k) D[dpos[k]] = (KT)0;
     }
   };
   RowChunk<KT> X0, X1, X2;
-  load_ptr(0);
-  load_chunk(X0, 0);
-  load_ptr(1);
-  load_chunk(X1, 1);
-  load_ptr(2);
+  RowPtr Q0, Q1, Q2;
+  load_ptr(Q0, 0);
+  load_chunk(X0, Q0, 0);
+  load_ptr(Q1, 1);
+  load_chunk(X1, Q1, 1);
+  load_ptr(Q2, 2);
   const int nb3 = (nb + 2) / 3 * 3;
   for (int t = 0; t < nb3; t += 3) {
-    block(t, X0, X2);
-    block(t + 1, X1, X0);
-    block(t + 2, X2, X1);
+    // block t uses rows X[t%3], loads rows t+2 into X[(t+2)%3] with pointers
+    // Q[(t+2)%3] and loads pointers t+3 into Q[t%3]
+    block(t, X0, X2, Q0, Q2);
+    block(t + 1, X1, X0, Q1, Q0);
+    block(t + 2, X2, X1, Q2, Q1);
   }
 }
 
@@ -474,7 +493,7 @@ VMC_PHASE SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, Smem& S,
   const bool unit_rhs = (rhs64 == nullptr);
   {
     KT* D = xs + align_up((size_t)n, 4);
-    for (int e = vmc_tid(); e < BLK * BLK; e += NT) D[e] = (KT)0;
+    for (int e = vmc_tid(); e < DTILE; e += NT) D[e] = (KT)0;
   }
   for (int r = vmc_tid(); r < n; r += NT)
     V[r] = unit_rhs ? (KT)(r == unit ? 1 : 0) : (KT)(rhs64[r] / beta);

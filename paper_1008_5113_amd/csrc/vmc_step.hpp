@@ -125,7 +125,7 @@ VMC_PHASE StepSolve wg_solve(const Walker& W, int m, const DevParams& P, Smem& S
     while (true) {
       PhaseClock pc;
       pc.start();
-      const size_t stage = align_up((size_t)W.n, 4) * 4 + (size_t)BLK * BLK * 4;
+      const size_t stage = align_up((size_t)W.n, 4) * 4 + align_up((size_t)DTILE * 4, 16);
       const double rn = wg_resid64(W, W.zvec, i, W.rvec, S, stage);
       o.ratio = wg_ratio(W, ulen, W.zvec, S);
       pc.stop(S, PH_RESID);

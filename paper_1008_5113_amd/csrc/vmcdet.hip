@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(NT, 4) k_phase(const Walker* __restrict__ walk
   KT* xs = (KT*)S.A;
   KT* D = xs + align_up((size_t)n, 4);
   KT* st = (KT*)S.stmp;
-  for (int e = threadIdx.x; e < BLK * BLK; e += NT) D[e] = (KT)0;
+  for (int e = threadIdx.x; e < DTILE; e += NT) D[e] = (KT)0;
   for (int r = threadIdx.x; r < n; r += NT) xs[r] = (KT)(1.0 / (1.0 + r));
   __syncthreads();
   const int m = states[w].m;
@@ -194,9 +194,9 @@ __global__ void __launch_bounds__(NT, 4) k_phase(const Walker* __restrict__ walk
       case 2: wg_usolve<KT>(W, Fac<KT>::usval(W), Fac<KT>::dinv(W), xs, D, st); break;
       case 3: wg_updates<KT>(W, m, P.m_max, xs, S); break;
       case 4: {
-        const size_t stage = align_up((size_t)n, 4) * 4 + (size_t)BLK * BLK * 4;
+        const size_t stage = align_up((size_t)n, 4) * 4 + align_up((size_t)DTILE * 4, 16);
         (void)wg_resid64(W, W.zvec, it % n, W.rvec, S, stage);
-        for (int e = threadIdx.x; e < BLK * BLK; e += NT) D[e] = (KT)0;
+        for (int e = threadIdx.x; e < DTILE; e += NT) D[e] = (KT)0;
         break;
       }
       case 5: (void)wg_ilutp(W, P, S); break;
