@@ -369,54 +369,54 @@ VMC_PHASE AT row_seg_dot(const RowSeg<VT>& g, int len, int sub, const XT* x) {
   return acc;
 }
 
-// w = A x (x in LDS or global), two rows per thread group per pass: both rows'
-// chunks are loaded before either is used, and the row lengths one pass
-// ahead.  Entries past 8*SPMV_CH (rows longer than the chunks cover) are
-// added by a strided tail loop.  When `resid` is set, writes e_unit - A x
-// instead and returns the partial sum of squares.
+// w = A x (x in LDS or global), RP rows per thread group per pass (3 for
+// FP32 values, 2 for FP64, as registers allow): all of a pass's row chunks
+// are loaded before any is used, and the row lengths one pass ahead.  Entries
+// past 8*SPMV_CH (rows longer than the chunks cover) are added by a strided
+// tail loop.  When `resid` is set, writes e_unit - A x instead and returns the
+// partial sum of squares.
 template <typename VT, typename XT, typename AT, typename OT>
 VMC_PHASE double wg_rows_apply(const Walker& W, const VT* aval, const XT* x, OT* out, int unit,
                                bool resid) {
+  constexpr int RP = sizeof(VT) == 4 ? 3 : 2;
   const int n = W.n, Wc = W.W;
   const int rr = vmc_tid() >> 3, sub = vmc_tid() & 7;
   double sq = 0.0;
   auto clamp_row = [&](int r) { return r < n ? r : 0; };
-  int l0 = W.a_len[clamp_row(rr)];
-  int l1 = W.a_len[clamp_row(rr + BLK)];
-  for (int base = 0; base < n; base += 2 * BLK) {
-    const int r0 = base + rr, r1 = r0 + BLK;
-    const int len0 = r0 < n ? l0 : 0, len1 = r1 < n ? l1 : 0;
-    RowSeg<VT> g0, g1;
-    const size_t o0 = (size_t)clamp_row(r0) * Wc, o1 = (size_t)clamp_row(r1) * Wc;
-    load_row_seg<VT>(g0, W.a_col + o0, aval + o0, len0, Wc, sub);
-    load_row_seg<VT>(g1, W.a_col + o1, aval + o1, len1, Wc, sub);
-    l0 = W.a_len[clamp_row(r0 + 2 * BLK)];
-    l1 = W.a_len[clamp_row(r1 + 2 * BLK)];
-    AT a0 = row_seg_dot<VT, XT, AT>(g0, len0, sub, x);
-    AT a1 = row_seg_dot<VT, XT, AT>(g1, len1, sub, x);
-    if (len0 > 8 * SPMV_CH || len1 > 8 * SPMV_CH) {
-      for (int e = 8 * SPMV_CH + sub; e < len0; e += 8) a0 += (AT)aval[o0 + e] * (AT)x[W.a_col[o0 + e]];
-      for (int e = 8 * SPMV_CH + sub; e < len1; e += 8) a1 += (AT)aval[o1 + e] * (AT)x[W.a_col[o1 + e]];
+  int ln[RP];
+#pragma unroll
+  for (int j = 0; j < RP; ++j) ln[j] = W.a_len[clamp_row(rr + j * BLK)];
+  for (int base = 0; base < n; base += RP * BLK) {
+    RowSeg<VT> g[RP];
+    int len[RP];
+    size_t off[RP];
+#pragma unroll
+    for (int j = 0; j < RP; ++j) {
+      const int r = base + rr + j * BLK;
+      len[j] = r < n ? ln[j] : 0;
+      off[j] = (size_t)clamp_row(r) * Wc;
+      load_row_seg<VT>(g[j], W.a_col + off[j], aval + off[j], len[j], Wc, sub);
     }
-    a0 = sum8(a0);
-    a1 = sum8(a1);
-    if (sub == 0) {
-      if (r0 < n) {
+#pragma unroll
+    for (int j = 0; j < RP; ++j) ln[j] = W.a_len[clamp_row(base + rr + (j + RP) * BLK)];
+    AT acc[RP];
+#pragma unroll
+    for (int j = 0; j < RP; ++j) acc[j] = row_seg_dot<VT, XT, AT>(g[j], len[j], sub, x);
+#pragma unroll
+    for (int j = 0; j < RP; ++j)
+      for (int e = 8 * SPMV_CH + sub; e < len[j]; e += 8)
+        acc[j] += (AT)aval[off[j] + e] * (AT)x[W.a_col[off[j] + e]];
+#pragma unroll
+    for (int j = 0; j < RP; ++j) {
+      const AT a = sum8(acc[j]);
+      const int r = base + rr + j * BLK;
+      if (sub == 0 && r < n) {
         if (resid) {
-          const double y = (r0 == unit ? 1.0 : 0.0) - (double)a0;
-          out[r0] = (OT)y;
+          const double y = (r == unit ? 1.0 : 0.0) - (double)a;
+          out[r] = (OT)y;
           sq += y * y;
         } else {
-          out[r0] = (OT)a0;
-        }
-      }
-      if (r1 < n) {
-        if (resid) {
-          const double y = (r1 == unit ? 1.0 : 0.0) - (double)a1;
-          out[r1] = (OT)y;
-          sq += y * y;
-        } else {
-          out[r1] = (OT)a1;
+          out[r] = (OT)a;
         }
       }
     }
