@@ -83,8 +83,14 @@ typedef struct vmc_params {
   double step;              /* proposal half-width h (uniform cube) */
   int32_t row_cap;          /* nonzeros per stored Slater row; <= 0: automatic */
   int32_t force_reorder_every; /* test knob: trigger every k-th step (0 = off) */
-  int32_t block_threads;    /* threads per walker workgroup (256 or 512; 0 = auto) */
-  int32_t reserved[7];
+  int32_t pad0;
+  double refactor_cost;     /* cost-balance refactor (Section 3.2): refactor once the
+                               stored-update vector entries streamed by preconditioner
+                               applications since the last factorisation reach this value
+                               (the expected cost of a new ILUTP in the same units); <= 0:
+                               refactor only after m_max updates.  vmc_autotune measures it
+                               per walker. */
+  int32_t reserved[6];
 } vmc_params;
 
 /* One walker: its physical system (orbital centres and shapes) and start. */
@@ -150,9 +156,22 @@ typedef struct vmc_stats {
                                updates, SpMV, orthogonalisation, solution, FP64 residual,
                                accept, refactor, reorder, whole persistent launch */
   double max_N, sum_N;
+  double update_entries;    /* stored-update vector entries streamed by all preconditioner
+                               applications (sum over solves of m * n * iterations) */
+  double refactor_cost;     /* the walker's current cost-balance threshold (<= 0: off) */
   int32_t status;           /* VMC_OK or the first error the walker hit */
   int32_t pad;
 } vmc_stats;
+
+/* What vmc_autotune measured or loaded. */
+typedef struct vmc_tune_info {
+  double ilutp_us_mean;      /* one ILUTP factorisation, mean over walkers (microseconds) */
+  double update_ns_per_entry;/* applying stored updates: time per vector entry (median) */
+  double refactor_cost_mean; /* resulting cost-balance thresholds, mean over walkers */
+  double step_us_min, step_us_max; /* trial step time per walker, extremes */
+  int32_t from_cache;        /* 1: thresholds came from cache_path, nothing was measured */
+  int32_t trial_steps;       /* steps every walker took during the measurement */
+} vmc_tune_info;
 
 /* Fill p with the defaults (Section 4 settings where the paper gives them). */
 vmc_status vmc_default_params(vmc_params* p);
@@ -201,11 +220,34 @@ vmc_status vmc_run_steps(void* ctx, int32_t steps, vmc_step_record* dev_log, int
    particle once); requires all walkers to share n.  Asynchronous. */
 vmc_status vmc_run_sweeps(void* ctx, int32_t sweeps, vmc_step_record* dev_log, int64_t log_cap);
 
+/* vmc_run_steps replayed from a HIP graph: the first call with a given
+   (steps, dev_log, log_cap) captures the persistent launch on the context's
+   stream into a graph; later calls with the same arguments launch that graph
+   (a different argument set re-captures).  Same results as vmc_run_steps.
+   Asynchronous. */
+vmc_status vmc_run_steps_graph(void* ctx, int32_t steps, vmc_step_record* dev_log, int64_t log_cap);
+
+/* Autotuner for the batch (Section 3.2 cost balance, and the walker-to-
+   workgroup map).  With a readable cache_path holding a threshold for every
+   walker size n in the context, loads those; otherwise measures on the device:
+   - one ILUTP factorisation of every walker (it counts as a refactor and
+     clears the update lists), timed per walker;
+   - trial_steps ordinary steps of every walker (they advance the chains),
+     from which the time per applied stored-update entry and the step time of
+     every walker are read;
+   and sets each walker's refactor_cost = ILUTP time / time per entry: a walker
+   refactors once its update applications have cost as much as a new
+   factorisation.  Walkers are then launched longest-step first.  Writes
+   cache_path (one line per n) when given and measured.  Synchronous.
+   info (host, may be NULL) receives the figures. */
+vmc_status vmc_autotune(void* ctx, const char* cache_path, int32_t trial_steps, vmc_tune_info* info);
+
 /* Diagnostic micro-benchmark: every walker's workgroup runs one phase of the
    solve `reps` times on its current matrix and factors, in one launch:
    0 SpMV (solve precision), 1 forward solve with L, 2 backward solve with U,
    3 rank-one update application, 4 FP64 residual e_i - A z, 5 ILUTP.
-   Phases 0-4 leave the walker state unchanged; 5 refactors.  Asynchronous. */
+   Phases 0-4 leave the walker state unchanged; 5 refactors (and clears the
+   update list, as any refactor does).  Asynchronous. */
 vmc_status vmc_phase_bench(void* ctx, int32_t phase, int32_t reps);
 
 /* Wait for all work issued on the context's stream; returns the first walker

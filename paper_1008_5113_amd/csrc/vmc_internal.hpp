@@ -151,6 +151,12 @@ struct WalkerState {
   long long st_steps, st_acc, st_solves, st_iters, st_reorders, st_refactors, st_nonconv;
   long long st_inner, st_refine, st_msum;
   double st_maxN, st_sumN;
+  // cost balance (Section 3.2): stored-update entries streamed by the
+  // preconditioner applications since the last factorisation, and the
+  // threshold at which a new factorisation is cheaper than going on
+  double upd_entries;
+  double refactor_cost;
+  double st_upd_entries;
   unsigned long long ph[PH_COUNT];
 };
 

@@ -239,12 +239,18 @@ VMC_PHASE void wg_det_ratio(const Walker& W, WalkerState* ws, const DevParams& P
       ws->st_inner += o.inner;
       ws->st_refine += o.passes;
       ws->st_msum += (long long)m * o.inner;
+      // one preconditioner application per GMRES iteration, each streaming
+      // the m stored update vectors
+      const double ent = (double)m * W.n * o.iters_total;
+      ws->upd_entries += ent;
+      ws->st_upd_entries += ent;
     }
     if (trig) {
       flags |= VMC_FLAG_REORDERED;
       st = wg_reorder_refactor<PREC>(W, P, S);
       if (vmc_tid() == 0) {
         ws->m = 0;
+        ws->upd_entries = 0.0;
         ws->st_reorders += 1;
         ws->st_refactors += 1;
       }
@@ -320,13 +326,17 @@ VMC_PHASE void wg_accept(const Walker& W, WalkerState* ws, const DevParams& P, S
     __threadfence_block();
     __syncthreads();
     const int m = ws->m;
-    if (m + 1 >= P.m_max) {
+    // refactor when the update list is full, or (cost balance, Section 3.2)
+    // once applying the stored updates has cost as much as a new ILUTP
+    const bool balance = ws->refactor_cost > 0.0 && ws->upd_entries >= ws->refactor_cost;
+    if (m + 1 >= P.m_max || balance) {
       pc.stop(S, PH_ACCEPT);
       st = wg_ilutp(W, P, S);
       pc.stop(S, PH_REFACTOR);
       flags |= VMC_FLAG_REFACTORED;
       if (vmc_tid() == 0) {
         ws->m = 0;
+        ws->upd_entries = 0.0;
         ws->st_refactors += 1;
       }
     } else {

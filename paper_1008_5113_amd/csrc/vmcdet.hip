@@ -11,6 +11,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -42,12 +45,18 @@ __global__ void __launch_bounds__(NT) k_setup(const Walker* __restrict__ walkers
   int st = WST_OK;
   if (mode & MODE_REORDER) wg_reorder(W, S);
   if (mode & (MODE_BUILD | MODE_REORDER)) st |= wg_build_all_rows(W, S);
-  if (st == WST_OK && (mode & MODE_ILUTP)) st = wg_ilutp(W, P, S);
+  PhaseClock pc;
+  pc.start();
+  if (st == WST_OK && (mode & MODE_ILUTP)) {
+    st = wg_ilutp(W, P, S);
+    pc.stop(S, PH_REFACTOR);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     WalkerState* ws = states + w;
     if (mode & MODE_ILUTP) {
       ws->m = 0;
+      ws->upd_entries = 0.0;
       ws->st_refactors += 1;
       if (mode & MODE_REORDER) ws->st_reorders += 1;
     }
@@ -139,9 +148,11 @@ __global__ void __launch_bounds__(NT) k_accept(const Walker* __restrict__ walker
 // Persistent fused path: `steps` Metropolis steps of one walker per workgroup.
 template <int PREC>
 __global__ void __launch_bounds__(NT, 4) k_run(const Walker* __restrict__ walkers, WalkerState* states,
-                                            DevParams P, int steps, vmc_step_record* log, long long log_cap) {
+                                            DevParams P, int steps, vmc_step_record* log, long long log_cap,
+                                            const int* order) {
   extern __shared__ __align__(16) char smem[];
-  const int w = blockIdx.x;
+  // workgroup -> walker: the autotuner's longest-first order, else identity
+  const int w = order ? order[blockIdx.x] : (int)blockIdx.x;
   const Walker& W = walkers[w];
   WalkerState* ws = states + w;
   Smem S = setup_smem(smem, W, P, PREC == VMC_PREC_FP64 ? 8 : 4);
@@ -204,6 +215,12 @@ __global__ void __launch_bounds__(NT, 4) k_phase(const Walker* __restrict__ walk
     }
     __syncthreads();
   }
+  if (phase == 5 && reps > 0 && threadIdx.x == 0) {
+    // a refactor: the stored updates belong to the old factors
+    states[w].m = 0;
+    states[w].upd_entries = 0.0;
+    states[w].st_refactors += reps;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -232,6 +249,16 @@ struct Ctx {
   unsigned char* d_acc = nullptr;
   int* d_err = nullptr;
   int* d_all = nullptr;
+  // workgroup -> walker order of the persistent launch (set by the autotuner)
+  int* d_order = nullptr;
+  bool use_order = false;
+  // graph of the persistent launch and the arguments it was captured with
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int g_steps = -1;
+  void* g_log = nullptr;
+  long long g_cap = -1;
+  bool g_order = false;
   std::string err;
 };
 
@@ -305,7 +332,7 @@ vmc_status vmc_default_params(vmc_params* p) {
   p->step = 0.25;
   p->row_cap = 0;
   p->force_reorder_every = 0;
-  p->block_threads = 0;
+  p->refactor_cost = 0.0;
   return VMC_OK;
 }
 
@@ -475,7 +502,13 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
       hipMalloc(&c->dS, sizeof(WalkerState) * n_walkers) != hipSuccess)
     return fail(VMC_ENOMEM, "device allocation failed");
   (void)hipMemcpy(c->dW, c->hw.data(), sizeof(Walker) * n_walkers, hipMemcpyHostToDevice);
-  (void)hipMemset(c->dS, 0, sizeof(WalkerState) * n_walkers);
+  {
+    std::vector<WalkerState> hs(n_walkers);
+    std::memset(hs.data(), 0, sizeof(WalkerState) * n_walkers);
+    for (auto& s : hs) s.refactor_cost = p->refactor_cost;
+    if (hipMemcpy(c->dS, hs.data(), sizeof(WalkerState) * n_walkers, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(VMC_EHIP, "initial copy failed");
+  }
   // staging buffers
   std::vector<int> all(n_walkers);
   for (int k = 0; k < n_walkers; ++k) all[k] = k;
@@ -487,6 +520,7 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
   ok &= hipMalloc(&c->d_dec, n_walkers) == hipSuccess;
   ok &= hipMalloc(&c->d_acc, n_walkers) == hipSuccess;
   ok &= hipMalloc(&c->d_err, sizeof(int) * n_walkers) == hipSuccess;
+  ok &= hipMalloc(&c->d_order, sizeof(int) * n_walkers) == hipSuccess;
   if (!ok) return fail(VMC_ENOMEM, "device allocation failed");
   (void)hipMemcpy(c->d_all, all.data(), sizeof(int) * n_walkers, hipMemcpyHostToDevice);
 
@@ -616,17 +650,53 @@ vmc_status vmc_accept(void* ctx, const int32_t* walkers, int32_t count, const ui
   return walker_errors(c);
 }
 
+static void launch_run(Ctx* c, int steps, vmc_step_record* dev_log, long long cap) {
+  const int* order = c->use_order ? c->d_order : nullptr;
+  if (c->dp.precision == VMC_PREC_FP64)
+    hipLaunchKernelGGL(k_run<VMC_PREC_FP64>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, steps,
+                       dev_log, cap, order);
+  else
+    hipLaunchKernelGGL(k_run<VMC_PREC_MIXED>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, steps,
+                       dev_log, cap, order);
+}
+
 vmc_status vmc_run_steps(void* ctx, int32_t steps, vmc_step_record* dev_log, int64_t log_cap) {
   Ctx* c = (Ctx*)ctx;
   if (!c || steps < 0) return VMC_EINVAL;
   if (steps == 0) return VMC_OK;
-  if (c->dp.precision == VMC_PREC_FP64)
-    hipLaunchKernelGGL(k_run<VMC_PREC_FP64>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, steps,
-                       dev_log, (long long)(dev_log ? log_cap : 0));
-  else
-    hipLaunchKernelGGL(k_run<VMC_PREC_MIXED>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, steps,
-                       dev_log, (long long)(dev_log ? log_cap : 0));
+  launch_run(c, steps, dev_log, (long long)(dev_log ? log_cap : 0));
   HIPCHK(c, hipGetLastError());
+  return VMC_OK;
+}
+
+vmc_status vmc_run_steps_graph(void* ctx, int32_t steps, vmc_step_record* dev_log, int64_t log_cap) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || steps < 0) return VMC_EINVAL;
+  if (steps == 0) return VMC_OK;
+  if (!c->stream) {
+    c->err = "vmc_run_steps_graph needs a context created on a non-default stream";
+    return VMC_EINVAL;
+  }
+  const long long cap = dev_log ? log_cap : 0;
+  if (!c->gexec || c->g_steps != steps || c->g_log != (void*)dev_log || c->g_cap != cap ||
+      c->g_order != c->use_order) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    launch_run(c, steps, dev_log, cap);
+    const hipError_t le = hipGetLastError();
+    const hipError_t ee = hipStreamEndCapture(c->stream, &c->graph);
+    HIPCHK(c, le);
+    HIPCHK(c, ee);
+    HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    c->g_steps = steps;
+    c->g_log = (void*)dev_log;
+    c->g_cap = cap;
+    c->g_order = c->use_order;
+  }
+  HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
   return VMC_OK;
 }
 
@@ -637,6 +707,118 @@ vmc_status vmc_run_sweeps(void* ctx, int32_t sweeps, vmc_step_record* dev_log, i
   const long long steps = (long long)sweeps * c->hw[0].n;
   if (steps > 0x7fffffffLL) { c->err = "too many steps"; return VMC_EINVAL; }
   return vmc_run_steps(ctx, (int32_t)steps, dev_log, log_cap);
+}
+
+// Cost-balance autotuner (Section 3.2: a new ILUTP once applying the stored
+// updates has cost as much as computing it), plus the longest-first launch
+// order of the walkers.  Per walker size n the thresholds are medians, so a
+// cache line per n reproduces them.
+vmc_status vmc_autotune(void* ctx, const char* cache_path, int32_t trial_steps, vmc_tune_info* info) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || trial_steps < 0) return VMC_EINVAL;
+  const int nw = c->nw;
+  vmc_tune_info ti;
+  std::memset(&ti, 0, sizeof(ti));
+  std::map<int, double> cached;
+  if (cache_path) {
+    std::ifstream f(cache_path);
+    int n;
+    double v;
+    while (f >> n >> v)
+      if (n > 0 && v > 0.0) cached[n] = v;
+  }
+  bool have_all = !cached.empty();
+  for (int w = 0; w < nw && have_all; ++w) have_all = cached.count(c->hw[w].n) > 0;
+  std::vector<double> cost(nw, 0.0), step_ticks(nw, 0.0);
+  if (have_all) {
+    for (int w = 0; w < nw; ++w) {
+      cost[w] = cached[c->hw[w].n];
+      step_ticks[w] = (double)c->hw[w].n * c->hw[w].W;  // model: bigger rows, longer steps
+    }
+    ti.from_cache = 1;
+  } else {
+    if (trial_steps < 1) {
+      c->err = "vmc_autotune: no cached thresholds for these walker sizes and trial_steps < 1";
+      return VMC_EINVAL;
+    }
+    std::vector<vmc_stats> s0(nw), s1(nw), s2(nw);
+    vmc_status st = vmc_get_stats(ctx, s0.data());
+    if (st) return st;
+    st = vmc_ilutp(ctx, nullptr, 0, 0);
+    if (st) return st;
+    st = vmc_get_stats(ctx, s1.data());
+    if (st) return st;
+    st = vmc_run_steps(ctx, trial_steps, nullptr, 0);
+    if (st) return st;
+    st = vmc_sync(ctx);
+    if (st) return st;
+    st = vmc_get_stats(ctx, s2.data());
+    if (st) return st;
+    // per walker size: median ILUTP ticks and median ticks per applied entry
+    std::map<int, std::vector<double>> ilu_by_n, ent_by_n;
+    for (int w = 0; w < nw; ++w) {
+      const int n = c->hw[w].n;
+      ilu_by_n[n].push_back((double)(s1[w].phase_ticks[PH_REFACTOR] - s0[w].phase_ticks[PH_REFACTOR]));
+      const double ent = s2[w].update_entries - s1[w].update_entries;
+      const double upd = (double)(s2[w].phase_ticks[PH_UPDATES] - s1[w].phase_ticks[PH_UPDATES]);
+      if (ent > 0.0) ent_by_n[n].push_back(upd / ent);
+      step_ticks[w] = (double)(s2[w].phase_ticks[PH_STEP] - s1[w].phase_ticks[PH_STEP]) / trial_steps;
+    }
+    auto median = [](std::vector<double> v) {
+      std::sort(v.begin(), v.end());
+      return v.empty() ? 0.0 : v[v.size() / 2];
+    };
+    std::map<int, double> per_n;
+    std::vector<double> all_ent;
+    for (auto& kv : ent_by_n) all_ent.insert(all_ent.end(), kv.second.begin(), kv.second.end());
+    const double ent_all = median(all_ent);
+    double ilu_sum = 0.0;
+    for (auto& kv : ilu_by_n) {
+      const double ilu = median(kv.second);
+      const double te = ent_by_n.count(kv.first) ? median(ent_by_n[kv.first]) : ent_all;
+      per_n[kv.first] = (ilu > 0.0 && te > 0.0) ? ilu / te : 0.0;
+      for (double x : kv.second) ilu_sum += x;
+    }
+    for (int w = 0; w < nw; ++w) cost[w] = per_n[c->hw[w].n];
+    ti.ilutp_us_mean = ilu_sum / nw / 100.0;          // 100 MHz wall clock
+    ti.update_ns_per_entry = ent_all * 10.0;
+    ti.trial_steps = trial_steps;
+    if (cache_path) {
+      std::ofstream f(cache_path);
+      f.precision(17);
+      for (auto& kv : per_n)
+        if (kv.second > 0.0) f << kv.first << " " << kv.second << "\n";
+    }
+  }
+  // thresholds into the walker states
+  std::vector<WalkerState> hs(nw);
+  HIPCHK(c, hipMemcpyAsync(hs.data(), c->dS, sizeof(WalkerState) * nw, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double csum = 0.0;
+  for (int w = 0; w < nw; ++w) {
+    hs[w].refactor_cost = cost[w];
+    csum += cost[w];
+  }
+  HIPCHK(c, hipMemcpyAsync(c->dS, hs.data(), sizeof(WalkerState) * nw, hipMemcpyHostToDevice, c->stream));
+  // longest step first, so the walkers that finish last start first
+  std::vector<int> order(nw);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return step_ticks[a] > step_ticks[b]; });
+  HIPCHK(c, hipMemcpyAsync(c->d_order, order.data(), sizeof(int) * nw, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->use_order = nw > 1;
+  ti.refactor_cost_mean = csum / nw;
+  if (!ti.from_cache) {
+    double mn = 1e300, mx = 0.0;
+    for (double t : step_ticks) {
+      mn = std::min(mn, t);
+      mx = std::max(mx, t);
+    }
+    ti.step_us_min = mn / 100.0;
+    ti.step_us_max = mx / 100.0;
+  }
+  if (info) *info = ti;
+  return VMC_OK;
 }
 
 vmc_status vmc_phase_bench(void* ctx, int32_t phase, int32_t reps) {
@@ -731,6 +913,8 @@ vmc_status vmc_get_stats(void* ctx, vmc_stats* out) {
     for (int k = 0; k < PH_COUNT && k < 12; ++k) o.phase_ticks[k] = (int64_t)s.ph[k];
     o.max_N = s.st_maxN;
     o.sum_N = s.st_sumN;
+    o.update_entries = s.st_upd_entries;
+    o.refactor_cost = s.refactor_cost;
     o.status = (s.status & WST_CAPACITY) ? VMC_ECAPACITY : (s.status & WST_SINGULAR) ? VMC_ESINGULAR : VMC_OK;
   }
   return VMC_OK;
@@ -757,6 +941,9 @@ vmc_status vmc_destroy(void* ctx) {
   (void)hipFree(c->d_dec);
   (void)hipFree(c->d_acc);
   (void)hipFree(c->d_err);
+  (void)hipFree(c->d_order);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
   delete c;
   return VMC_OK;
 }

@@ -43,6 +43,7 @@ EXPORTED = [
     "vmc_default_params", "vmc_create", "vmc_build_slater", "vmc_ilutp", "vmc_det_ratio",
     "vmc_accept", "vmc_run_steps", "vmc_run_sweeps", "vmc_sync", "vmc_get_dims",
     "vmc_get_state", "vmc_get_stats", "vmc_last_error", "vmc_destroy", "vmc_phase_bench",
+    "vmc_run_steps_graph", "vmc_autotune",
 ]
 PHASE_BENCH = {"spmv": 0, "lsolve": 1, "usolve": 2, "updates": 3, "resid64": 4, "ilutp": 5}
 
@@ -65,8 +66,9 @@ class VmcParams(ctypes.Structure):
         ("step", ctypes.c_double),
         ("row_cap", ctypes.c_int32),
         ("force_reorder_every", ctypes.c_int32),
-        ("block_threads", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("pad0", ctypes.c_int32),
+        ("refactor_cost", ctypes.c_double),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 
@@ -125,7 +127,17 @@ class VmcStats(ctypes.Structure):
         ("refine_passes", ctypes.c_int64), ("update_sum", ctypes.c_int64),
         ("phase_ticks", ctypes.c_int64 * 12),
         ("max_N", ctypes.c_double), ("sum_N", ctypes.c_double),
+        ("update_entries", ctypes.c_double), ("refactor_cost", ctypes.c_double),
         ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
+    ]
+
+
+class VmcTuneInfo(ctypes.Structure):
+    _fields_ = [
+        ("ilutp_us_mean", ctypes.c_double), ("update_ns_per_entry", ctypes.c_double),
+        ("refactor_cost_mean", ctypes.c_double), ("step_us_min", ctypes.c_double),
+        ("step_us_max", ctypes.c_double), ("from_cache", ctypes.c_int32),
+        ("trial_steps", ctypes.c_int32),
     ]
 
 
@@ -152,6 +164,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.vmc_last_error.restype = ctypes.c_char_p
     lib.vmc_destroy.argtypes = [P]
     lib.vmc_phase_bench.argtypes = [P, i32, i32]
+    lib.vmc_run_steps_graph.argtypes = [P, i32, P, ctypes.c_int64]
+    lib.vmc_autotune.argtypes = [P, ctypes.c_char_p, i32, ctypes.POINTER(VmcTuneInfo)]
     for name in EXPORTED:
         if name != "vmc_last_error":
             getattr(lib, name).restype = i32
@@ -299,20 +313,28 @@ class Context:
         self._check(lib().vmc_accept(self.h, _ptr(w), count, _ptr(dec), _ptr(out)))
         return out.astype(bool)
 
-    def run_steps(self, steps: int, log_device_ptr: Optional[int] = None, log_cap: int = 0):
-        self._check(lib().vmc_run_steps(self.h, int(steps),
-                                        ctypes.c_void_p(log_device_ptr) if log_device_ptr else None,
-                                        int(log_cap)))
+    def run_steps(self, steps: int, log_device_ptr: Optional[int] = None, log_cap: int = 0,
+                  graph: bool = False):
+        fn = lib().vmc_run_steps_graph if graph else lib().vmc_run_steps
+        self._check(fn(self.h, int(steps), ctypes.c_void_p(log_device_ptr) if log_device_ptr else None,
+                       int(log_cap)))
 
-    def run_steps_logged(self, steps: int):
+    def run_steps_logged(self, steps: int, graph: bool = False):
         """Run and return the step log as a numpy structured array [walker, step]."""
         import torch
         cap = self.n_walkers * steps
         buf = torch.empty(cap * STEP_RECORD_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
-        self.run_steps(steps, buf.data_ptr(), cap)
+        self.run_steps(steps, buf.data_ptr(), cap, graph=graph)
         self.sync()
         arr = buf.cpu().numpy().view(STEP_RECORD_DTYPE)
         return arr.reshape(self.n_walkers, steps)
+
+    def autotune(self, trial_steps: int = 100, cache_path: Optional[str] = None) -> dict:
+        """Cost-balance thresholds and launch order (see vmc_autotune)."""
+        info = VmcTuneInfo()
+        self._check(lib().vmc_autotune(self.h, cache_path.encode() if cache_path else None,
+                                       int(trial_steps), ctypes.byref(info)))
+        return {f[0]: getattr(info, f[0]) for f in VmcTuneInfo._fields_}
 
     def phase_bench(self, phase: str, reps: int):
         self._check(lib().vmc_phase_bench(self.h, PHASE_BENCH[phase], int(reps)))

@@ -291,3 +291,65 @@ def test_full_size_stress_n8192(vm):
     _say("case: full size stress n=8192 x 64 walkers")
     inst = wl.stress_n8192()
     _full_config(vm, inst, 60, (0,))
+
+
+def test_graph_replays_match_direct_launches(vm):
+    """The persistent launch captured in a HIP graph and replayed three times
+    (with ordinary host work and synchronisation between replays) gives the
+    same step records as three direct launches."""
+    _say("case: graph replays vs direct launches")
+    import torch
+    inst = wl.fp64_n1024(8)
+    direct = vm.Context.from_instance(inst)
+    direct.ilutp(reorder=True)
+    stream = torch.cuda.Stream()
+    graphed = vm.Context.from_instance(inst, stream=stream.cuda_stream)
+    graphed.ilutp(reorder=True)
+    graphed.sync()
+    for rep in range(3):
+        a = direct.run_steps_logged(40)
+        b = graphed.run_steps_logged(40, graph=True)
+        _ = np.linalg.norm(a["ratio"])  # host work between replays
+        assert np.array_equal(a["ratio"], b["ratio"]), rep
+        assert np.array_equal(a["flags"], b["flags"]), rep
+        assert np.array_equal(a["step"], b["step"]), rep
+    direct.close()
+    graphed.close()
+
+
+def test_autotune_cost_balance(vm, tmp_path):
+    """The autotuner sets positive cost-balance thresholds and a launch order;
+    refactors then follow the balance rule, the chain stays exact, and a
+    second context loads the same thresholds from the cache file."""
+    _say("case: autotune")
+    inst = wl.fp64_n1024(4)
+    cache = str(tmp_path / "tune.txt")
+    ctx = vm.Context.from_instance(inst, walkers=[0, 1, 2, 3], m_max=160)
+    ctx.ilutp(reorder=True)
+    info = ctx.autotune(trial_steps=60, cache_path=cache)
+    _say(f"  {info}")
+    assert info["from_cache"] == 0 and info["ilutp_us_mean"] > 0 and info["update_ns_per_entry"] > 0
+    st = ctx.stats()
+    costs = [s["refactor_cost"] for s in st]
+    assert all(c > 0 for c in costs)
+    # chain after tuning: replay the next 300 steps with the oracle
+    pos0 = ctx.state(0)["pos"]
+    g0 = int(ctx.state(0)["step"])
+    log = ctx.run_steps_logged(300)
+    rep = replay(inst.systems[0], pos0, inst.walkers[0].seed, inst.params.step, _records(log[0]),
+                 dec_tol=DEC_TOL, mode="sm")
+    assert int(log[0]["step"][0]) == g0
+    assert rep.pos_mismatch == 0 and rep.decision_mismatch_outside_tol == 0
+    assert rep.max_dlog < DLOG_TOL
+    refac = np.sum((log["flags"] & 4) != 0)
+    assert refac > 0
+    ctx.close()
+    ctx2 = vm.Context.from_instance(inst, walkers=[0, 1], m_max=160)
+    ctx2.ilutp(reorder=True)
+    info2 = ctx2.autotune(trial_steps=0, cache_path=cache)
+    assert info2["from_cache"] == 1
+    # one walker size: every walker got the same (median) threshold, which the
+    # cache reproduces
+    assert max(costs) == min(costs)
+    assert all(abs(s["refactor_cost"] - costs[0]) <= 1e-12 * costs[0] for s in ctx2.stats())
+    ctx2.close()
