@@ -84,7 +84,7 @@ def factor_nnz(ctx, walkers):
     return acc / len(walkers)
 
 
-def run_path(inst, precision, steps, warmup, chunk, walkers, stream_ptr, **kw):
+def run_path(inst, precision, steps, warmup, chunk, walkers, stream_ptr, tune_steps=0, **kw):
     import torch
     import paper_1008_5113_amd as vm
     t0 = time.time()
@@ -93,6 +93,11 @@ def run_path(inst, precision, steps, warmup, chunk, walkers, stream_ptr, **kw):
     ctx.sync()
     log(f"precision={precision}: set-up (create + reorder + ILUTP of {len(walkers)} walkers) "
         f"{time.time() - t0:.1f}s")
+    tune = None
+    if tune_steps:
+        t1 = time.time()
+        tune = ctx.autotune(trial_steps=tune_steps)
+        log(f"precision={precision}: autotune ({tune_steps} trial steps) {time.time() - t1:.1f}s: {tune}")
     if warmup:
         t1 = time.time()
         for _ in range(warmup // chunk):
@@ -132,7 +137,7 @@ def run_path(inst, precision, steps, warmup, chunk, walkers, stream_ptr, **kw):
         reorders=d("reorders"), refactors=d("refactors"), nonconverged=d("nonconverged"),
         max_N=max(b["max_N"] for b in s1), nnz_per_row=(nnz / n).tolist(),
         phase_us_per_walker_step={k: round(v, 2) for k, v in phase_us.items()},
-        alg_bytes=bytes_, alg_bytes_per_launch=bytes_ / nl,
+        alg_bytes=bytes_, alg_bytes_per_launch=bytes_ / nl, autotune=tune,
         alg_gbs=bytes_ / (sum(launch_ms) / 1e3) / 1e9,
         status=[b["status"] for b in s1 if b["status"] != 0][:4])
     ctx.close()
@@ -238,6 +243,8 @@ def main():
     ap.add_argument("--walkers", type=int, default=0, help="0: the workload's count")
     ap.add_argument("--paths", default="mixed,fp64")
     ap.add_argument("--m-max", type=int, default=0, help="stored updates before a refactor (0: workload)")
+    ap.add_argument("--autotune", type=int, default=0,
+                    help="trial steps of the cost-balance autotuner before warm-up (0: fixed m_max)")
     ap.add_argument("--cpu-procs", type=int, default=8)
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -286,7 +293,8 @@ def main():
         prec = vm.PREC_MIXED if path == "mixed" else vm.PREC_FP64
         log(f"path {path}: {nw} walkers, n={inst.systems[0].n}, {args.steps} timed steps")
         kw = {"m_max": args.m_max} if args.m_max else {}
-        results[path] = run_path(inst, prec, args.steps, args.warmup, args.chunk, walkers, stream_ptr, **kw)
+        results[path] = run_path(inst, prec, args.steps, args.warmup, args.chunk, walkers, stream_ptr,
+                                 tune_steps=args.autotune, **kw)
         log(f"path {path}: {json.dumps(results[path])}")
     head = results.get("mixed") or results[next(iter(results))]
     headpath = "mixed" if "mixed" in results else next(iter(results))

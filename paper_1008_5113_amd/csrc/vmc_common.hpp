@@ -50,12 +50,12 @@ __host__ __device__ inline size_t ilutp_lds_bytes(int n) {
 __host__ __device__ inline LdsLayout lds_layout(int n, int ktb, int maxit, int mmax) {
   LdsLayout L;
   size_t o = align_up((size_t)n, 4) * ktb + align_up((size_t)DTILE * ktb, 16);  // xs, D
-  L.hb = o; o += (MAXIT + 2) * 8;
-  L.cs = o; o += (MAXIT + 1) * 8;
-  L.sn = o; o += (MAXIT + 1) * 8;
-  L.gg = o; o += (MAXIT + 2) * 8;
+  L.hb = o; o += (size_t)(maxit + 2) * 8;
+  L.cs = o; o += (size_t)(maxit + 1) * 8;
+  L.sn = o; o += (size_t)(maxit + 1) * 8;
+  L.gg = o; o += (size_t)(maxit + 2) * 8;
   L.rp = o; o += (size_t)maxit * (maxit + 1) / 2 * 8 + 8;
-  L.yb = o; o += (MAXIT + 1) * 8;
+  L.yb = o; o += (size_t)(maxit + 1) * 8;
   L.gb = o; o += (size_t)(mmax + 1) * 8;
   L.cb = o; o += (size_t)(mmax + 1) * 8;
   size_t a = o;
@@ -65,7 +65,7 @@ __host__ __device__ inline LdsLayout lds_layout(int n, int ktb, int maxit, int m
   if (reo > a) a = reo;
   o = align_up(a, 16);
   L.regionA = 0;
-  L.red = o; o += (size_t)NWAVE * (MAXIT + 2) * 8;
+  L.red = o; o += (size_t)NWAVE * (maxit + 2) * 8;
   L.sc = o; o += 32 * 8;
   L.ic = o; o += 32 * 4;
   L.stmp = o; o += BLK * 8;
