@@ -191,15 +191,22 @@ VMC_PHASE void wg_trisolve_rows(const Walker& W, const int* ptr, const unsigned 
       for (int k = 0; k < PF; ++k) D[dpos[k]] = (KT)0;
     }
   };
+  // forward substitution of a unit vector e_unit: every row above the unit's
+  // block solves to zero, so the sweep starts at that block
+  const int t0 = (FORWARD && !aux && unit >= 0 && unit < n) ? unit / BLK : 0;
+  if (t0 > 0) {
+    for (int r = vmc_tid(); r < t0 * BLK; r += NT) xs[r] = (KT)0;
+    __syncthreads();
+  }
   RowChunk<KT> X0, X1, X2;
   RowPtr Q0, Q1, Q2;
-  load_ptr(Q0, 0);
-  load_chunk(X0, Q0, 0);
-  load_ptr(Q1, 1);
-  load_chunk(X1, Q1, 1);
-  load_ptr(Q2, 2);
-  const int nb3 = (nb + 2) / 3 * 3;
-  for (int t = 0; t < nb3; t += 3) {
+  load_ptr(Q0, t0);
+  load_chunk(X0, Q0, t0);
+  load_ptr(Q1, t0 + 1);
+  load_chunk(X1, Q1, t0 + 1);
+  load_ptr(Q2, t0 + 2);
+  const int nb3 = t0 + (nb - t0 + 2) / 3 * 3;
+  for (int t = t0; t < nb3; t += 3) {
     // block t uses rows X[t%3], loads rows t+2 into X[(t+2)%3] with pointers
     // Q[(t+2)%3] and loads pointers t+3 into Q[t%3]
     block(t, X0, X2, Q0, Q2);
@@ -369,47 +376,51 @@ VMC_PHASE AT row_seg_dot(const RowSeg<VT>& g, int len, int sub, const XT* x) {
   return acc;
 }
 
-// w = A x (x in LDS or global), RP rows per thread group per pass (3 for
-// FP32 values, 2 for FP64, as registers allow): all of a pass's row chunks
-// are loaded before any is used, and the row lengths one pass ahead.  Entries
-// past 8*SPMV_CH (rows longer than the chunks cover) are added by a strided
-// tail loop.  When `resid` is set, writes e_unit - A x instead and returns the
-// partial sum of squares.
+// w = A x (x in LDS or global).  A pass covers RP row groups of 64 rows (8
+// threads per row; RP = 1, as registers allow).
+// Passes are software-pipelined in two register sets with fixed roles: the
+// next pass's row chunks are in flight while the current one is consumed, and
+// the row lengths are loaded two passes ahead.  Entries past 8*SPMV_CH (rows
+// longer than the chunks cover) are added by a strided tail loop.  When
+// `resid` is set, writes e_unit - A x instead and returns the partial sum of
+// squares.
 template <typename VT, typename XT, typename AT, typename OT>
 VMC_PHASE double wg_rows_apply(const Walker& W, const VT* aval, const XT* x, OT* out, int unit,
                                bool resid) {
-  constexpr int RP = sizeof(VT) == 4 ? 3 : 2;
+  constexpr int RP = 1;
   const int n = W.n, Wc = W.W;
   const int rr = vmc_tid() >> 3, sub = vmc_tid() & 7;
+  constexpr int PSTEP = RP * BLK;
   double sq = 0.0;
   auto clamp_row = [&](int r) { return r < n ? r : 0; };
-  int ln[RP];
-#pragma unroll
-  for (int j = 0; j < RP; ++j) ln[j] = W.a_len[clamp_row(rr + j * BLK)];
-  for (int base = 0; base < n; base += RP * BLK) {
+  struct Pass {
     RowSeg<VT> g[RP];
     int len[RP];
-    size_t off[RP];
+  };
+  auto load_lens = [&](int* ln, int base) {
+#pragma unroll
+    for (int j = 0; j < RP; ++j) ln[j] = W.a_len[clamp_row(base + rr + j * BLK)];
+  };
+  auto issue = [&](Pass& P, int base, const int* ln) {
 #pragma unroll
     for (int j = 0; j < RP; ++j) {
       const int r = base + rr + j * BLK;
-      len[j] = r < n ? ln[j] : 0;
-      off[j] = (size_t)clamp_row(r) * Wc;
-      load_row_seg<VT>(g[j], W.a_col + off[j], aval + off[j], len[j], Wc, sub);
+      P.len[j] = r < n ? ln[j] : 0;
+      const size_t o = (size_t)clamp_row(r) * Wc;
+      load_row_seg<VT>(P.g[j], W.a_col + o, aval + o, P.len[j], Wc, sub);
     }
-#pragma unroll
-    for (int j = 0; j < RP; ++j) ln[j] = W.a_len[clamp_row(base + rr + (j + RP) * BLK)];
-    AT acc[RP];
-#pragma unroll
-    for (int j = 0; j < RP; ++j) acc[j] = row_seg_dot<VT, XT, AT>(g[j], len[j], sub, x);
-#pragma unroll
-    for (int j = 0; j < RP; ++j)
-      for (int e = 8 * SPMV_CH + sub; e < len[j]; e += 8)
-        acc[j] += (AT)aval[off[j] + e] * (AT)x[W.a_col[off[j] + e]];
+  };
+  auto consume = [&](const Pass& P, int base) {
 #pragma unroll
     for (int j = 0; j < RP; ++j) {
-      const AT a = sum8(acc[j]);
       const int r = base + rr + j * BLK;
+      AT acc = row_seg_dot<VT, XT, AT>(P.g[j], P.len[j], sub, x);
+      if (P.len[j] > 8 * SPMV_CH) {
+        const size_t o = (size_t)clamp_row(r) * Wc;
+        for (int e = 8 * SPMV_CH + sub; e < P.len[j]; e += 8)
+          acc += (AT)aval[o + e] * (AT)x[W.a_col[o + e]];
+      }
+      const AT a = sum8(acc);
       if (sub == 0 && r < n) {
         if (resid) {
           const double y = (r == unit ? 1.0 : 0.0) - (double)a;
@@ -420,6 +431,22 @@ VMC_PHASE double wg_rows_apply(const Walker& W, const VT* aval, const XT* x, OT*
         }
       }
     }
+  };
+  int lnA[RP], lnB[RP];
+  load_lens(lnA, 0);
+  load_lens(lnB, PSTEP);
+  Pass PA, PB;
+  issue(PA, 0, lnA);
+  load_lens(lnA, 2 * PSTEP);
+  const int npass = (n + PSTEP - 1) / PSTEP;
+  const int npass2 = (npass + 1) / 2 * 2;
+  for (int p = 0; p < npass2; p += 2) {
+    issue(PB, (p + 1) * PSTEP, lnB);
+    load_lens(lnB, (p + 3) * PSTEP);
+    consume(PA, p * PSTEP);
+    issue(PA, (p + 2) * PSTEP, lnA);
+    load_lens(lnA, (p + 4) * PSTEP);
+    consume(PB, (p + 1) * PSTEP);
   }
   return sq;
 }
