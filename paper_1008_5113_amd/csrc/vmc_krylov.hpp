@@ -474,23 +474,46 @@ VMC_PHASE double wg_resid64(const Walker& W, const double* z, int unit, double* 
   __syncthreads();
   return sqrt(wg_sum(sq, S.red));
 }
-
 // h[i] = sum_r w[r] V_i[r] for i < cnt (FP64 reduction), written to out[] (LDS).
+// Up to four dot products share one pass over w.  With vdiff set, the same
+// first pass also accumulates ||vdiff - w||^2 (FP64) into out[cnt].
 template <typename KT>
-VMC_PHASE void wg_dots(const KT* w, const KT* V, int n, int cnt, double* out, Smem& S) {
+VMC_PHASE void wg_dots(const KT* w, const KT* V, int n, int cnt, double* out, Smem& S,
+                       const KT* vdiff = nullptr) {
   __syncthreads();
-  for (int i = 0; i < cnt; ++i) {
-    KT acc = 0;
-    const KT* vi = V + (size_t)i * n;
-    for (int r = vmc_tid(); r < n; r += NT) acc += w[r] * vi[r];
-    const double s = wave_sum((double)acc);
-    if (lane_id() == 0) S.red[i * NWAVE + wave_id()] = s;
+  for (int i0 = 0; i0 < cnt; i0 += 4) {
+    const int c = min(4, cnt - i0);
+    const bool withd = vdiff && i0 == 0;
+    KT acc[4] = {(KT)0, (KT)0, (KT)0, (KT)0};
+    double dn = 0.0;
+    for (int r = vmc_tid(); r < n; r += NT) {
+      const KT wr = w[r];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q < c) acc[q] += wr * V[(size_t)(i0 + q) * n + r];
+      if (withd) {
+        const double d = (double)vdiff[r] - (double)wr;
+        dn += d * d;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q < c) {
+        const double sq = wave_sum((double)acc[q]);
+        if (lane_id() == 0) S.red[(i0 + q) * NWAVE + wave_id()] = sq;
+      }
+    }
+    if (withd) {
+      const double sq = wave_sum(dn);
+      if (lane_id() == 0) S.red[cnt * NWAVE + wave_id()] = sq;
+    }
   }
   __syncthreads();
-  for (int i = vmc_tid(); i < cnt; i += NT) {
-    double s = 0.0;
-    for (int k = 0; k < NWAVE; ++k) s += S.red[i * NWAVE + k];
-    out[i] = s;
+  const int tot = cnt + (vdiff ? 1 : 0);
+  for (int i = vmc_tid(); i < tot; i += NT) {
+    double sq = 0.0;
+    for (int k = 0; k < NWAVE; ++k) sq += S.red[i * NWAVE + k];
+    out[i] = sq;
   }
   __syncthreads();
 }
@@ -540,17 +563,11 @@ VMC_PHASE SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, Smem& S,
     wg_spmv<KT>(W, aval, xs, w);
     __syncthreads();
     pc.stop(S, PH_SPMV);
-    // effective stability: ||v_j - A M v_j||
-    double nl = 0.0;
-    for (int r = vmc_tid(); r < n; r += NT) {
-      const double d = (double)vj[r] - (double)w[r];
-      nl += d * d;
-    }
-    const double Nj = sqrt(wg_sum(nl, S.red));
-    N = fmax(N, Nj);
-    // classical Gram-Schmidt, twice
+    // classical Gram-Schmidt, twice; the first pass also gives the effective
+    // stability term ||v_j - A M v_j||
     double* h = S.hb;
-    wg_dots<KT>(w, V, n, j + 1, h, S);
+    wg_dots<KT>(w, V, n, j + 1, h, S, vj);
+    N = fmax(N, sqrt(h[j + 1]));
     for (int r = vmc_tid(); r < n; r += NT) {
       KT x = w[r];
       for (int i = 0; i <= j; ++i) x -= (KT)h[i] * V[(size_t)i * n + r];
