@@ -236,58 +236,93 @@ VMC_PHASE void wg_updates(const Walker& W, int m, int mmax, KT* xs, Smem& S) {
   if (m <= 0) return;
   const int n = W.n;
   const KT* upv = Fac<KT>::upval(W);
-  for (int s0 = 0; s0 < m; s0 += NT / 4) {
-    const int s = s0 + (vmc_tid() >> 2), part = vmc_tid() & 3;
+  constexpr int TPS = 8;  // threads per stored update in the two small products
+  // g_s = u_s^T x (u_s sparse): every thread issues four loads at a time,
+  // branch-free (indices clamped to a valid entry, products masked)
+  for (int s0 = 0; s0 < m; s0 += NT / TPS) {
+    const int s = s0 + (vmc_tid() >> 3), part = vmc_tid() & (TPS - 1);
+    const int sc = s < m ? s : 0;
+    const int len = s < m ? W.up_len[sc] : 0;
+    const int* uc = W.up_col + (size_t)sc * W.UC;
+    const KT* uv = upv + (size_t)sc * W.UC;
     KT acc = 0;
-    if (s < m) {
-      const int len = W.up_len[s];
-      const int* uc = W.up_col + (size_t)s * W.UC;
-      const KT* uv = upv + (size_t)s * W.UC;
-#pragma unroll 4
-      for (int e = part; e < len; e += 4) acc += uv[e] * xs[uc[e]];
+    for (int e0 = part; e0 < len; e0 += 4 * TPS) {
+      int cc[4];
+      KT vv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = e0 + q * TPS;
+        const int ec = e < len ? e : 0;
+        cc[q] = uc[ec];
+        vv[q] = uv[ec];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const KT xv = xs[cc[q]];
+        acc += (e0 + q * TPS < len) ? vv[q] * xv : (KT)0;
+      }
     }
-    acc = sum4(acc);
+    acc = sum8(acc);
     if (s < m && part == 0) S.gb[s] = (double)acc;
   }
   __syncthreads();
-  for (int s = vmc_tid(); s < m; s += NT) {
-    const double* Gs = W.T + (size_t)s * mmax;
+  // c = G g with G = (I + T)^{-1} lower triangular (FP64)
+  for (int s0 = 0; s0 < m; s0 += NT / TPS) {
+    const int s = s0 + (vmc_tid() >> 3), part = vmc_tid() & (TPS - 1);
+    const int sc = s < m ? s : 0;
+    const double* Gs = W.T + (size_t)sc * mmax;
+    const int tl = s < m ? s + 1 : 0;
     double c = 0.0;
-#pragma unroll 8
-    for (int t = 0; t <= s; ++t) c += Gs[t] * S.gb[t];
-    S.cb[s] = c;
+    for (int t0 = part; t0 < tl; t0 += 4 * TPS) {
+      double gv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int t = t0 + q * TPS;
+        gv[q] = Gs[t < tl ? t : 0];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int t = t0 + q * TPS;
+        c += (t < tl) ? gv[q] * S.gb[t < tl ? t : 0] : 0.0;
+      }
+    }
+    c = sum8(c);
+    if (s < m && part == 0) S.cb[s] = c;
   }
   __syncthreads();
+  // x -= Z c: every thread keeps RPT rows in registers and streams four
+  // stored vectors at a time with unconditional (clamped) loads
   const KT* Z = Fac<KT>::Z(W);
-  constexpr int RPT = 8;  // rows per thread held in registers
+  constexpr int RPT = 4;
   for (int rb = 0; rb < n; rb += NT * RPT) {
     KT xr[RPT];
+    int rc[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int r = rb + k * NT + vmc_tid();
-      xr[k] = (r < n) ? xs[r] : (KT)0;
+      rc[k] = r < n ? r : 0;
+      xr[k] = xs[rc[k]];
     }
     int s = 0;
     for (; s + 4 <= m; s += 4) {
       const KT c0 = (KT)S.cb[s], c1 = (KT)S.cb[s + 1], c2 = (KT)S.cb[s + 2], c3 = (KT)S.cb[s + 3];
       const KT* z0 = Z + (size_t)s * n;
+      KT a0[RPT], a1[RPT], a2[RPT], a3[RPT];
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
-        const int r = rb + k * NT + vmc_tid();
-        if (r < n) {
-          const KT a0 = z0[r], a1 = z0[n + r], a2 = z0[2 * (size_t)n + r], a3 = z0[3 * (size_t)n + r];
-          xr[k] -= a0 * c0 + a1 * c1 + a2 * c2 + a3 * c3;
-        }
+        a0[k] = z0[rc[k]];
+        a1[k] = z0[n + rc[k]];
+        a2[k] = z0[2 * (size_t)n + rc[k]];
+        a3[k] = z0[3 * (size_t)n + rc[k]];
       }
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) xr[k] -= a0[k] * c0 + a1[k] * c1 + a2[k] * c2 + a3[k] * c3;
     }
     for (; s < m; ++s) {
       const KT c0 = (KT)S.cb[s];
       const KT* z0 = Z + (size_t)s * n;
 #pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int r = rb + k * NT + vmc_tid();
-        if (r < n) xr[k] -= z0[r] * c0;
-      }
+      for (int k = 0; k < RPT; ++k) xr[k] -= z0[rc[k]] * c0;
     }
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
