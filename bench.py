@@ -60,7 +60,7 @@ def algorithmic_bytes(stats0, stats1, nnz, n, mixed: bool):
     return tot
 
 
-def measured_traffic(path, workload, chunk, walkers, m_max):
+def measured_traffic(path, workload, chunk, walkers, m_max, autotune):
     """HBM bytes per launch of the step kernel from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy
     calibration), or None when that summary was taken on other kernel sources
@@ -72,7 +72,7 @@ def measured_traffic(path, workload, chunk, walkers, m_max):
     with open(f) as fh:
         d = json.load(fh)
     same = (d.get("source_hash") == kernel_source_hash()
-            and d.get("launch") == {"chunk": chunk, "walkers": walkers, "m_max": m_max})
+            and d.get("launch") == {"chunk": chunk, "walkers": walkers, "m_max": m_max, "autotune": autotune})
     return d["hbm_bytes_per_launch"] if same else None
 
 
@@ -235,16 +235,18 @@ def phase_bench(inst, precision, walkers, stream_ptr, reps, warm_steps, **kw):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=400)
+    ap.add_argument("--steps", type=int, default=800)
+    ap.add_argument("--warmup", type=int, default=800)
     ap.add_argument("--chunk", type=int, default=0,
                     help="steps per launch of the persistent kernel (0: --steps, one timed launch)")
     ap.add_argument("--workload", default="mixed_n4000")
     ap.add_argument("--walkers", type=int, default=0, help="0: the workload's count")
     ap.add_argument("--paths", default="mixed,fp64")
-    ap.add_argument("--m-max", type=int, default=0, help="stored updates before a refactor (0: workload)")
-    ap.add_argument("--autotune", type=int, default=0,
-                    help="trial steps of the cost-balance autotuner before warm-up (0: fixed m_max)")
+    ap.add_argument("--m-max", type=int, default=0,
+                    help="cap on stored updates (0: the workload's, or 200 when autotuning)")
+    ap.add_argument("--autotune", type=int, default=200,
+                    help="trial steps of the cost-balance autotuner before warm-up (0: refactor after a "
+                         "fixed m_max updates only)")
     ap.add_argument("--cpu-procs", type=int, default=8)
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -266,6 +268,8 @@ def main():
         return
     if args.chunk <= 0:
         args.chunk = args.steps
+    if not args.m_max and args.autotune:
+        args.m_max = 200  # a cap only: the tuned cost balance decides when to refactor
     if args.steps % args.chunk or args.warmup % args.chunk:
         ap.error("--steps and --warmup must be multiples of --chunk")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -312,6 +316,8 @@ def main():
         "dtype": "f32+f64" if headpath == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": inst.systems[0].n, "walkers": nw,
+                   "refactor": (f"cost balance, autotuned over {args.autotune} trial steps, cap {args.m_max}"
+                                if args.autotune else f"every {args.m_max or inst.params.m_max} updates"),
                    "lattice": "x".join(str(x) for x in inst.systems[0].lattice),
                    "path": headpath, "step": "one Metropolis step of every walker"},
         "paths": results,
@@ -321,7 +327,7 @@ def main():
     out["roofline"] = {"bound": "hbm", "achieved": head["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": head["alg_gbs"] / HBM_PEAK_GBS,
                        "traffic": measured_traffic(headpath, args.workload, args.chunk, nw,
-                                                   args.m_max or inst.params.m_max),
+                                                   args.m_max or inst.params.m_max, args.autotune),
                        "kernel": f"k_run<{1 if headpath == 'mixed' else 0}> (persistent fused step kernel), "
                                  f"{args.chunk} steps x {nw} walkers per launch",
                        "launch_ms_avg": head["launch_ms_avg"],

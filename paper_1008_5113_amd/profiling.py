@@ -155,6 +155,7 @@ def main():
     s.add_argument("--chunk", type=int, required=True, help="steps per launch in the profiled run")
     s.add_argument("--walkers", type=int, required=True)
     s.add_argument("--m-max", type=int, required=True)
+    s.add_argument("--autotune", type=int, required=True, help="autotuner trial steps of the run (0: none)")
     s.add_argument("--out-json", required=True)
     s.add_argument("--out-md", default=None)
     s.add_argument("--commands", default=None, help="text file holding the profiling commands")
@@ -162,7 +163,7 @@ def main():
     args = ap.parse_args()
     if args.cmd != "summarize":
         ap.error("summarize is the only command")
-    launch = {"chunk": args.chunk, "walkers": args.walkers, "m_max": args.m_max}
+    launch = {"chunk": args.chunk, "walkers": args.walkers, "m_max": args.m_max, "autotune": args.autotune}
     out = summarize(args.trace, args.fetch, args.write, args.copy_fetch, args.copy_write, args.prec, launch)
     with open(args.out_json, "w") as f:
         json.dump(out, f, indent=1)
