@@ -244,9 +244,10 @@ def main():
     ap.add_argument("--paths", default="mixed,fp64")
     ap.add_argument("--m-max", type=int, default=0,
                     help="cap on stored updates (0: the workload's, or 200 when autotuning)")
-    ap.add_argument("--autotune", type=int, default=200,
-                    help="trial steps of the cost-balance autotuner before warm-up (0: refactor after a "
-                         "fixed m_max updates only)")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: run the cost-balance autotuner before warm-up, over one launch of --chunk "
+                         "steps (so every launch of the step kernel has the same size); 0: refactor after "
+                         "a fixed m_max updates only")
     ap.add_argument("--cpu-procs", type=int, default=8)
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -298,7 +299,7 @@ def main():
         log(f"path {path}: {nw} walkers, n={inst.systems[0].n}, {args.steps} timed steps")
         kw = {"m_max": args.m_max} if args.m_max else {}
         results[path] = run_path(inst, prec, args.steps, args.warmup, args.chunk, walkers, stream_ptr,
-                                 tune_steps=args.autotune, **kw)
+                                 tune_steps=args.chunk if args.autotune else 0, **kw)
         log(f"path {path}: {json.dumps(results[path])}")
     head = results.get("mixed") or results[next(iter(results))]
     headpath = "mixed" if "mixed" in results else next(iter(results))
@@ -316,7 +317,7 @@ def main():
         "dtype": "f32+f64" if headpath == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": inst.systems[0].n, "walkers": nw,
-                   "refactor": (f"cost balance, autotuned over {args.autotune} trial steps, cap {args.m_max}"
+                   "refactor": (f"cost balance, autotuned over {args.chunk} trial steps, cap {args.m_max}"
                                 if args.autotune else f"every {args.m_max or inst.params.m_max} updates"),
                    "lattice": "x".join(str(x) for x in inst.systems[0].lattice),
                    "path": headpath, "step": "one Metropolis step of every walker"},
