@@ -23,6 +23,7 @@ from typing import List
 
 import numpy as np
 
+from .energy import kinetic_energy
 from .geometry import orbital_values, propose, slater_dense
 from .ratio import StandardAlgorithm, ratio_lu
 from .rng import step_draws
@@ -64,6 +65,31 @@ def free_run(system, pos0, seed: int, h: float, n_steps: int, start_step: int = 
             A[p] = new_row
             pos[p] = rnew
     return out, pos
+
+
+def sweep_energies(system, pos0, seed: int, h: float, sweeps: int, start_step: int = 0,
+                   mode: str = "sm"):
+    """Free run of whole sweeps, sampling the kinetic energy per particle
+    (eq. (energyEq)) at the end of every sweep (Section 4).  Returns the list
+    of energies, the acceptance count and the final positions."""
+    n = system.n
+    pos = np.array(pos0, dtype=np.float64, copy=True)
+    energies, accepted = [], 0
+    for s in range(sweeps):
+        recs, pos = free_run(system, pos, seed, h, n, start_step=start_step + s * n, mode=mode)
+        accepted += sum(1 for r in recs if r.accepted)
+        energies.append(kinetic_energy(pos, system))
+    return energies, accepted, pos
+
+
+def positions_after(pos0, log):
+    """Positions after following a step log (records with particle, new_pos,
+    accepted) from pos0."""
+    pos = np.array(pos0, dtype=np.float64, copy=True)
+    for rec in log:
+        if rec.accepted:
+            pos[int(rec.particle)] = np.asarray(rec.new_pos, dtype=np.float64)
+    return pos
 
 
 @dataclasses.dataclass

@@ -1,0 +1,137 @@
+"""Pins for the oracle's kinetic energy (Section 2.3; Section 4, eq. (energyEq)).
+
+- the orbital Laplacians against finite differences of the orbital values;
+- the per-particle terms -(1/2) lap_p Psi / Psi against finite differences of
+  the Slater determinant itself (numpy's slogdet), for the plain Gaussians,
+  the Gaussian + p-like orbitals and the paper's b.c.c. k = 1 orbitals;
+- one particle and one orbital: the paper's closed form (6k - 4k^2 d^2)/2;
+- the chain average on the paper's smallest system against the paper's table.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle.chain import sweep_energies
+from oracle.energy import kinetic_energy, kinetic_terms, laplacian_values
+from oracle.geometry import dist2, orbital_values, slater_dense
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+H = 1e-3
+STENCIL = ((-2, -1.0), (-1, 16.0), (1, 16.0), (2, -1.0))  # with -30 f(0), over 12 h^2
+
+
+def _systems():
+    return {
+        "gauss": wl.make_system((4, 4, 4), sigma=0.35, cutoff=2.0),
+        "gauss_px": wl.make_system((4, 4, 4), sigma=0.35, kind=wl.ORB_GAUSS_PX, p_scale=0.1,
+                                   p_sigma=0.5, cutoff=2.0),
+        "paper_bcc": wl.paper_bcc(K=4, n_walkers=1).systems[0],
+    }
+
+
+def _far_from_cutoff(r, s, margin):
+    d = np.sqrt(dist2(np.asarray(r)[None, :], s.sites, s.box))
+    return np.all(np.abs(d - s.cutoff) > margin)
+
+
+@pytest.mark.parametrize("name", ["gauss", "gauss_px", "paper_bcc"])
+def test_laplacian_matches_finite_differences(name):
+    s = _systems()[name]
+    rng = np.random.default_rng(7)
+    checked = 0
+    while checked < 6:
+        r = rng.uniform(0.0, 1.0, 3) * s.box
+        if not _far_from_cutoff(r, s, 4 * H):
+            continue
+        f0 = orbital_values(r, s)
+        fd = np.zeros_like(f0)
+        for c in range(3):
+            acc = -30.0 * f0
+            for k, w in STENCIL:
+                rr = r.copy()
+                rr[c] += k * H
+                acc = acc + w * orbital_values(rr, s)
+            fd += acc / (12.0 * H * H)
+        lap = laplacian_values(r, s)
+        scale = np.max(np.abs(lap))
+        assert np.max(np.abs(lap - fd)) <= 1e-6 * scale
+        assert np.all(lap[f0 == 0.0] == 0.0)
+        checked += 1
+
+
+@pytest.mark.parametrize("name", ["gauss", "gauss_px", "paper_bcc"])
+def test_kinetic_terms_match_determinant_finite_differences(name):
+    s = _systems()[name]
+    rng = np.random.default_rng(11)
+    pos = wl.initial_positions(s.sites, s.box, 3, 0.3)
+    A = slater_dense(pos, s)
+    sign0, log0 = np.linalg.slogdet(A)
+    # only the moved particle's row changes: test particles whose stencil stays
+    # clear of every cutoff sphere (the truncated orbitals jump there)
+    clear = [p for p in range(s.n) if _far_from_cutoff(pos[p], s, 4 * H)]
+    assert len(clear) >= 12
+    ps = rng.choice(np.asarray(clear), size=12, replace=False)
+    t = kinetic_terms(pos, s, particles=ps)
+    for k, p in enumerate(ps):
+        lap_ratio = 0.0
+        for c in range(3):
+            acc = -30.0
+            for off, w in STENCIL:
+                A2 = A.copy()
+                r = pos[p].copy()
+                r[c] += off * H
+                A2[p] = orbital_values(r, s)
+                sg, lg = np.linalg.slogdet(A2)
+                acc += w * sg * sign0 * np.exp(lg - log0)
+            lap_ratio += acc / (12.0 * H * H)
+        fd = -0.5 * lap_ratio
+        assert abs(t[k] - fd) <= 2e-6 * max(1.0, abs(fd)), (p, t[k], fd)
+    # the whole-system energy is the mean of the terms
+    assert abs(kinetic_energy(pos, s) - np.mean(kinetic_terms(pos, s))) < 1e-14
+
+
+def test_single_orbital_closed_form():
+    # one particle, one Gaussian exp(-k|d|^2) (sigma^2 = 1/(2k)): the
+    # paper's eq. (energyEq) with n = 1 is (6k - 4k^2 |d|^2)/2
+    k = 1.7
+    s = wl.make_system((1, 1, 1), a=4.0, sigma=1.0 / np.sqrt(2.0 * k), cutoff=1.9)
+    for d in [0.0, 0.3, 0.8, 1.2]:
+        pos = np.array([[d * 0.6, d * 0.8, 0.0]]) % s.box
+        e = kinetic_energy(pos, s)
+        ref = 0.5 * (6.0 * k - 4.0 * k * k * d * d)
+        assert abs(e - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+def _paper_table():
+    rows = {}
+    with open(os.path.join(GOLDEN, "energy_table.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            n, es, ss, ep, sp = line.split()
+            rows[int(n)] = (float(es), float(ss), float(ep), float(sp))
+    return rows
+
+
+def test_chain_energy_matches_paper_table():
+    """The oracle's chain on the paper's n = 686 system reproduces the paper's
+    kinetic energy within the statistical error of the two runs: 50 sweeps of
+    one walker, the first 10 discarded, the average over the other 40 compared
+    with E = 2.0984 (sigma 0.0075).  Plausible mistakes (a lost factor 1/2, a
+    sign, k for 1/sigma^2, the exchange part of A^{-1}) move it by 0.3 or more."""
+    table = _paper_table()
+    e_ref, sig_ref = table[686][0], table[686][1]
+    inst = wl.paper_bcc(K=7, n_walkers=1)
+    s = inst.systems[0]
+    w = inst.walkers[0]
+    es, acc, _ = sweep_energies(s, w.pos0, w.seed, inst.params.step, 50)
+    tail = np.asarray(es[10:])
+    # error of the mean from blocks of 10 sweeps (the chain is autocorrelated)
+    blocks = tail.reshape(-1, 10).mean(axis=1)
+    sig_ours = blocks.std(ddof=1) / np.sqrt(len(blocks))
+    tol = 4.0 * np.hypot(sig_ours, sig_ref)
+    assert abs(tail.mean() - e_ref) <= tol, (tail.mean(), sig_ours)
+    assert 0.5 < acc / (50 * s.n) < 0.7

@@ -6,14 +6,17 @@ workload. It contains none of the method's arithmetic (no orbital evaluation,
 no Slater matrix, no ratio, no solver).  Both the CPU oracle and the GPU path
 consume what it returns.
 
-Lattice convention: a simple-cubic lattice of ``Lx x Ly x Lz`` sites with
-spacing ``a``; site ``j = ix + Lx*(iy + Ly*iz)`` sits at ``(ix, iy, iz)*a`` in a
-periodic box ``(Lx*a, Ly*a, Lz*a)``.  Particle ``p`` starts at site ``p`` plus a
-uniform jitter and is wrapped into ``[0, L)`` per axis.
+Lattice convention: ``Lx x Ly x Lz`` cubic cells of side ``a`` in a periodic
+box ``(Lx*a, Ly*a, Lz*a)``, each holding ``nb`` sites at the fractional offsets
+``basis[b]`` (one site at the corner for simple cubic; the corner and the body
+centre for b.c.c.).  Site ``j = b + nb*(ix + Lx*(iy + Ly*iz))`` sits at
+``((ix, iy, iz) + basis[b])*a``.  Particle ``p`` starts at site ``p`` plus a
+jitter and is wrapped into ``[0, L)`` per axis.
 
-The paper's own workload is Gaussian orbitals on a b.c.c. lattice (Section 2.1,
-eq. (gaussian); Section 4).  The named workloads below use a simple-cubic
-lattice with a geometric cutoff instead, and are synthetic in the same way the
+The paper's own workload is Gaussian orbitals exp(-k|d|^2), k = 1, on a b.c.c.
+lattice of cube side 2.031 with n = 2K^3 (Section 2.1, eq. (gaussian);
+Section 4): ``paper_bcc`` below.  The other named workloads use a simple-cubic
+lattice with a geometric cutoff instead.  All are synthetic in the same way the
 paper's are: there is no dataset behind them.
 
 All transcendental set-up draws (Gaussian site jitter, lognormal widths) are
@@ -30,6 +33,9 @@ import numpy as np
 ORB_GAUSS = 0      # phi_j(r) = exp(-|d|^2 / (2 sigma_j^2))
 ORB_GAUSS_PX = 1   # Gaussian plus p_scale * d_x * exp(-|d|^2 / (2 p_sigma^2))
 
+SC_BASIS = ((0.0, 0.0, 0.0),)
+BCC_BASIS = ((0.0, 0.0, 0.0), (0.5, 0.5, 0.5))
+
 SETUP_STREAM = 1   # Philox key word 1 used for per-walker set-up draws
 SYSTEM_STREAM = 2  # Philox key word 1 used for shared-system draws
 
@@ -37,14 +43,15 @@ SYSTEM_STREAM = 2  # Philox key word 1 used for shared-system draws
 @dataclasses.dataclass
 class System:
     """One physical system: orbital centres and orbital shapes."""
-    lattice: tuple            # (Lx, Ly, Lz) site counts
-    a: float                  # lattice spacing
+    lattice: tuple            # (Lx, Ly, Lz) cell counts
+    a: float                  # cell side
     sites: np.ndarray         # (n, 3) float64, wrapped into [0, L)
     sigma: np.ndarray         # (n,) float64 Gaussian widths per orbital
     kind: int                 # ORB_GAUSS or ORB_GAUSS_PX
     p_scale: float
     p_sigma: float
     cutoff: float
+    basis: tuple = SC_BASIS   # fractional site offsets within a cell
 
     @property
     def n(self) -> int:
@@ -58,14 +65,12 @@ class System:
     def site_margin(self) -> float:
         """Largest per-axis deviation of a site from its nominal lattice point
         (minimum image), so a lattice-neighbourhood search can be widened."""
-        n = self.n
-        Lx, Ly, _ = self.lattice
-        j = np.arange(n)
-        nominal = np.stack([(j % Lx), (j // Lx) % Ly, j // (Lx * Ly)], axis=1) * self.a
+        Lx, Ly, Lz = self.lattice
+        nominal = lattice_sites(Lx, Ly, Lz, self.a, self.basis)
         d = self.sites - nominal
         box = self.box
         d = d - box * np.round(d / box)
-        return float(np.max(np.abs(d))) if n else 0.0
+        return float(np.max(np.abs(d))) if self.n else 0.0
 
 
 @dataclasses.dataclass
@@ -110,9 +115,13 @@ def _gen(seed: int, stream: int) -> np.random.Generator:
     return np.random.Generator(np.random.Philox(key=np.array([seed, stream], dtype=np.uint64)))
 
 
-def lattice_sites(Lx: int, Ly: int, Lz: int, a: float = 1.0) -> np.ndarray:
-    j = np.arange(Lx * Ly * Lz)
-    return np.stack([(j % Lx), (j // Lx) % Ly, j // (Lx * Ly)], axis=1).astype(np.float64) * a
+def lattice_sites(Lx: int, Ly: int, Lz: int, a: float = 1.0, basis=SC_BASIS) -> np.ndarray:
+    nb = len(basis)
+    j = np.arange(Lx * Ly * Lz * nb)
+    cell = j // nb
+    frac = np.stack([(cell % Lx), (cell // Lx) % Ly, cell // (Lx * Ly)], axis=1).astype(np.float64)
+    frac = frac + np.asarray(basis, dtype=np.float64)[j % nb]
+    return frac * a
 
 
 def wrap(x: np.ndarray, box: np.ndarray) -> np.ndarray:
@@ -123,16 +132,23 @@ def wrap(x: np.ndarray, box: np.ndarray) -> np.ndarray:
 
 
 def initial_positions(sites: np.ndarray, box: np.ndarray, seed: int, jitter: float,
-                      gen: Optional[np.random.Generator] = None) -> np.ndarray:
+                      gen: Optional[np.random.Generator] = None, normal: bool = False) -> np.ndarray:
+    """Sites plus a jitter: uniform on [-jitter, jitter]^3, or normal with
+    standard deviation ``jitter`` per axis (wrapped, so it may exceed a box)."""
     g = gen if gen is not None else _gen(seed, SETUP_STREAM)
+    if normal:
+        d = g.normal(0.0, jitter, size=sites.shape)
+        x = np.mod(sites + d, box)
+        return np.where(x >= box, x - box, x)
     d = g.uniform(-jitter, jitter, size=sites.shape)
     return wrap(sites + d, box)
 
 
 def make_system(lattice, a=1.0, sigma=0.35, kind=ORB_GAUSS, p_scale=0.0, p_sigma=0.5,
-                cutoff=2.0, site_jitter_sd=0.0, sigma_lognormal_sd=0.0, seed=0) -> System:
+                cutoff=2.0, site_jitter_sd=0.0, sigma_lognormal_sd=0.0, seed=0,
+                basis=SC_BASIS) -> System:
     Lx, Ly, Lz = lattice
-    sites = lattice_sites(Lx, Ly, Lz, a)
+    sites = lattice_sites(Lx, Ly, Lz, a, basis)
     n = sites.shape[0]
     box = np.array([Lx * a, Ly * a, Lz * a])
     g = _gen(seed, SYSTEM_STREAM)
@@ -143,7 +159,8 @@ def make_system(lattice, a=1.0, sigma=0.35, kind=ORB_GAUSS, p_scale=0.0, p_sigma
     else:
         sig = np.full(n, float(sigma))
     return System(lattice=(Lx, Ly, Lz), a=a, sites=sites, sigma=sig.astype(np.float64),
-                  kind=kind, p_scale=p_scale, p_sigma=p_sigma, cutoff=cutoff)
+                  kind=kind, p_scale=p_scale, p_sigma=p_sigma, cutoff=cutoff,
+                  basis=tuple(tuple(float(x) for x in b) for b in basis))
 
 
 # ---------------------------------------------------------------------------
@@ -216,10 +233,38 @@ def small_instance(lattice=(4, 4, 4), n_walkers=1, sigma=0.35, cutoff=2.0, kind=
     return Instance("small", [s], ws, Params(step=step, **pkw))
 
 
+PAPER_BCC_A = 2.031          # cube side (Section 4)
+PAPER_K = 1.0                # Gaussian decay rate k of eq. (gaussian)
+PAPER_DROP = 1e-5            # entries below 1e-5 * max|a_ij| are dropped (Section 4)
+
+
+def paper_bcc(K: int = 7, n_walkers: int = 64, step: float = 0.55, sweeps: int = 120) -> Instance:
+    """The paper's experiment (Section 4): n = 2K^3 electrons, Gaussian orbitals
+    exp(-k|d|^2) with k = 1 on a b.c.c. lattice of K^3 cubes of side 2.031,
+    entries below 1e-5 times the largest dropped, ILUTP droptol 0.01 and
+    permtol 0.05, GMRES rtol 1e-6 and at most 40 iterations, reorder when
+    N > 100 or the iterations reach four times their average, 120 sweeps, FP64.
+
+    Readings: the largest entry is taken as 1 (an orbital at its own centre),
+    so the drop rule is the geometric cutoff |d|^2 <= ln(1e5)/k; the proposal
+    half-width (not given) is chosen so the acceptance is near the paper's
+    0.588; start positions are the sites plus normal jitter of standard
+    deviation 1/(2 sqrt(k)) per axis, the spread of an isolated |phi|^2."""
+    sigma = 1.0 / np.sqrt(2.0 * PAPER_K)
+    cutoff = float(np.sqrt(np.log(1.0 / PAPER_DROP) / PAPER_K))
+    s = make_system((K, K, K), a=PAPER_BCC_A, sigma=sigma, cutoff=cutoff, basis=BCC_BASIS)
+    jit = 0.5 / np.sqrt(PAPER_K)
+    ws = [Walker(0, initial_positions(s.sites, s.box, w, jit, normal=True), w) for w in range(n_walkers)]
+    return Instance("paper_bcc_n%d" % s.n, [s], ws,
+                    Params(step=step, sweeps=sweeps, droptol=0.01, permtol=0.05, gmres_rtol=1e-6,
+                           gmres_maxit=40, n_thresh=100.0, iter_factor=4.0, mixed=False))
+
+
 WORKLOADS = {
     "plain_n128": plain_n128,
     "fp64_n1024": fp64_n1024,
     "uneven_batch": uneven_batch,
     "mixed_n4000": mixed_n4000,
     "stress_n8192": stress_n8192,
+    "paper_bcc": paper_bcc,
 }
