@@ -70,7 +70,7 @@ typedef struct vmc_params {
   int32_t precision;        /* VMC_PREC_FP64 or VMC_PREC_MIXED */
   int32_t gmres_maxit;      /* full GMRES, no restart (Section 4: 40); <= 64 */
   double gmres_rtol;        /* FP64 path: stop when ||r|| <= rtol * ||b|| */
-  double droptol;           /* ILUTP relative drop tolerance (times ||a_i||_2) */
+  double droptol;           /* ILUTP relative drop tolerance (see ilu_drop_norm) */
   double permtol;           /* ILUTP: swap columns when permtol*|max| > |diag| */
   int32_t lfil;             /* extra fill per L row and per U row; < 0: ceil(nnz/(2n)) */
   int32_t m_max;            /* stored rank-one updates before a refactor (>= 1) */
@@ -90,17 +90,28 @@ typedef struct vmc_params {
                                (the expected cost of a new ILUTP in the same units); <= 0:
                                refactor only after m_max updates.  vmc_autotune measures it
                                per walker. */
-  int32_t reserved[6];
+  int32_t ilu_work_cap;     /* ILUTP work-row capacity (entries of one row during its
+                               elimination, candidates, multipliers before the fill
+                               limit); <= 0: 512 entries, 192 candidates, 160 multipliers.
+                               Larger values fit matrices with more fill (e.g. the paper's
+                               b.c.c. k = 1 orbitals at droptol 0.01 need about 9 K^2);
+                               fewer rows are then factored concurrently so the LDS fits.
+                               At most 8192.  Rows beyond it give VMC_ECAPACITY. */
+  int32_t ilu_drop_norm;    /* ILUTP drop scale of row i: 0 = droptol * ||a_i||_2; 1 =
+                               droptol * ||a_i||_1 / nnz(a_i), the mean magnitude that
+                               SPARSKIT's ILUTP (the paper's preconditioner, Section 4) uses */
+  int32_t reserved[4];
 } vmc_params;
 
 /* One walker: its physical system (orbital centres and shapes) and start. */
 typedef struct vmc_walker_init {
-  int32_t n;                /* particles = orbitals, 1 <= n <= 16384 */
-  int32_t lattice[3];       /* site counts per axis; box = lattice * a */
-  double a;                 /* lattice spacing */
-  double site_margin;       /* max per-axis distance of a site from its lattice point */
-  const double* sites;      /* host, n*3, orbital centres in [0, box) (site j nominally at
-                               (j % Lx, (j / Lx) % Ly, j / (Lx*Ly)) * a) */
+  int32_t n;                /* particles = orbitals, 1 <= n <= 16384; n = n_basis*Lx*Ly*Lz */
+  int32_t lattice[3];       /* cell counts per axis (Lx, Ly, Lz); box = lattice * a */
+  double a;                 /* cell side */
+  double site_margin;       /* max per-axis distance of a site from its nominal position */
+  const double* sites;      /* host, n*3, orbital centres in [0, box); site
+                               j = b + n_basis*(ix + Lx*(iy + Ly*iz)) sits nominally at
+                               ((ix, iy, iz) + basis[b]) * a */
   const double* sigma;      /* host, n, Gaussian width of each orbital */
   int32_t orbital_kind;     /* VMC_ORB_* */
   double p_scale;
@@ -108,6 +119,11 @@ typedef struct vmc_walker_init {
   double cutoff;            /* orbital j vanishes where the minimum-image distance > cutoff */
   const double* pos0;       /* host, n*3, initial positions in [0, box) */
   uint64_t seed;            /* Philox key word 0 for this walker's draws */
+  int32_t n_basis;          /* sites per cell, 0..4; 0 is read as 1 with basis[0] = 0
+                               (simple cubic).  The paper's lattice is b.c.c. (Section 2.1,
+                               Section 4): two sites, offsets (0,0,0) and (1/2,1/2,1/2) */
+  int32_t pad0;
+  double basis[4][3];       /* fractional offsets of the cell's sites, each in [0, 1) */
 } vmc_walker_init;
 
 /* Per-step outcome, also used as the record of the step log. */
@@ -226,6 +242,33 @@ vmc_status vmc_run_sweeps(void* ctx, int32_t sweeps, vmc_step_record* dev_log, i
    (a different argument set re-captures).  Same results as vmc_run_steps.
    Asynchronous. */
 vmc_status vmc_run_steps_graph(void* ctx, int32_t steps, vmc_step_record* dev_log, int64_t log_cap);
+
+/* Kinetic energy (Section 2.3, Local Energy; Section 4, eq. (energyEq)), with
+   hbar = m = 1.  For particle p, replacing row i(p) of the Slater matrix by the
+   kinetic row -(1/2) lap phi_j(r_p) gives the term
+     t_p = -(1/2) lap_p Psi / Psi = lkin_p^T A^{-1} e_{i(p)},
+   obtained by one more solve A z = e_{i(p)} with the same preconditioned GMRES
+   (mixed refinement included) and the same reorder triggers as a ratio; the
+   energy per particle is E = (1/n) sum_p t_p.  Terms are computed for the
+   particle ids p_begin <= p < p_end (clamped to each walker's n) of the listed
+   walkers (walkers NULL: all, count ignored), at their current positions.
+   energy_out (host, count): (sum of the computed terms) / n, i.e. E when the
+   range covers every particle.  terms_out (host, may be NULL): the terms, walker
+   after walker in list order, each walker's in particle order.  A walker with a
+   pending ratio (vmc_det_ratio without vmc_accept) gives VMC_ESTATE.  A solve may
+   reorder and refactor the walker, as a step does.  Synchronous. */
+vmc_status vmc_kinetic_energy(void* ctx, const int32_t* walkers, int32_t count, int32_t p_begin, int32_t p_end,
+                              double* energy_out, double* terms_out);
+
+/* vmc_run_steps that also samples the kinetic energy per particle E at the end
+   of every sweep (whenever the step count becomes a multiple of n), as
+   Section 4 does.  All walkers must share n and their step count.  The k-th
+   sample of this call goes to dev_energy[w * energy_cap + k] (device memory,
+   n_walkers * energy_cap doubles) while k < energy_cap; dev_log as for
+   vmc_run_steps.  Reads the step counts from the device first (one
+   synchronisation), then runs asynchronously. */
+vmc_status vmc_run_steps_energy(void* ctx, int32_t steps, vmc_step_record* dev_log, int64_t log_cap,
+                                double* dev_energy, int32_t energy_cap);
 
 /* Autotuner for the batch (Section 3.2 cost balance, and the walker-to-
    workgroup map).  With a readable cache_path holding a threshold for every

@@ -12,7 +12,10 @@ largest entry of the row, searching the entire row (Section 4).
 Row i is computed as follows (readings of the paper's settings in brackets):
 
 1. w <- row i of A, keyed by original column; tau_i = droptol * ||a_i||_2
-   [relative drop tolerance: the 2-norm of the original row];
+   [relative drop tolerance: the 2-norm of the original row], or, with
+   norm="mean_abs", droptol * ||a_i||_1 / nnz(a_i), the mean magnitude of the
+   row's entries, which is the scale SPARSKIT's ILUT and ILUTP use (Section 4
+   names SPARSKIT's ILUTP as the paper's preconditioner);
 2. eliminate: repeatedly take the not-yet-visited entry of w whose column sits
    at the smallest position k < i, divide it by U_kk; drop it if its magnitude
    is below tau_i, otherwise store it as l_ik and subtract l_ik times row k of U
@@ -49,8 +52,14 @@ def paper_lfil(nnz: int, n: int) -> int:
     return int(math.ceil(nnz / (2.0 * n)))
 
 
-def ilutp(rows, n: int, droptol: float, permtol: float, lfil: int):
+def ilutp(rows, n: int, droptol: float, permtol: float, lfil: int, norm: str = "l2",
+          scales: bool = False):
     """Factor the sparse matrix given as ``rows`` (list of {col: value}).
+    ``norm`` selects the drop scale of step 1: "l2" or "mean_abs".  With
+    ``scales`` also returns, for every stored entry, the magnitude its value
+    was accumulated from (|a_ij| plus the |l_ik u_kj| of every multiplier that
+    updated it, including multipliers the fill limit later removed), the scale
+    of its rounding error.
 
     Returns (L, U, q): L[i] = {k: l_ik} strictly lower (positions), U[i] =
     {k: u_ik} upper including the diagonal (positions), q[k] = original column
@@ -60,13 +69,20 @@ def ilutp(rows, n: int, droptol: float, permtol: float, lfil: int):
     pos = list(range(n))
     Urows = [None] * n      # original column labels
     Lrows = [None] * n
+    Uscale = [None] * n
+    Lscale = [None] * n
     for i in range(n):
         a = rows[i]
-        tau = droptol * math.sqrt(sum(v * v for v in a.values()))
+        if norm == "mean_abs":
+            tau = droptol * sum(abs(v) for v in a.values()) / len(a)
+        else:
+            tau = droptol * math.sqrt(sum(v * v for v in a.values()))
         nL0 = sum(1 for c in a if pos[c] < i)
         nU0 = sum(1 for c in a if pos[c] > i)
         w = dict(a)
+        wabs = {c: abs(v) for c, v in a.items()}
         Lrow = {}
+        Lsc = {}
         visited = set()
         while True:
             cand = [pos[c] for c in w if pos[c] < i and pos[c] not in visited]
@@ -75,13 +91,17 @@ def ilutp(rows, n: int, droptol: float, permtol: float, lfil: int):
             k = min(cand)
             visited.add(k)
             c = q[k]
-            lik = w.pop(c) / Urows[k][c]
+            wk = w.pop(c)
+            lik = wk / Urows[k][c]
+            sk = wabs.pop(c)
             if abs(lik) < tau:
                 continue
             Lrow[k] = lik
+            Lsc[k] = (sk + abs(wk) * Uscale[k][c] / abs(Urows[k][c])) / abs(Urows[k][c])
             for c2, v in Urows[k].items():
                 if c2 != c:
                     w[c2] = w.get(c2, 0.0) - lik * v
+                    wabs[c2] = wabs.get(c2, 0.0) + abs(lik * v) + abs(lik) * Uscale[k][c2]
         # w now holds only columns at positions >= i
         cdiag = q[i]
         off = [(c, v) for c, v in w.items() if c != cdiag and abs(v) >= tau]
@@ -109,7 +129,12 @@ def ilutp(rows, n: int, droptol: float, permtol: float, lfil: int):
         if urow.get(q[i], 0.0) == 0.0:
             raise SingularPivot(f"zero pivot at row {i}")
         Urows[i] = urow
+        Uscale[i] = {c: wabs[c] for c in urow}
+        Lscale[i] = {k: Lsc[k] for k in Lrows[i]}
     U = [{pos[c]: v for c, v in Urows[i].items()} for i in range(n)]
+    if scales:
+        Us = [{pos[c]: v for c, v in Uscale[i].items()} for i in range(n)]
+        return Lrows, U, np.array(q), Lscale, Us
     return Lrows, U, np.array(q)
 
 

@@ -19,25 +19,30 @@ struct LdsLayout {
 
 __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// ILUTP: ILU_R rows are factored concurrently, one wave each, every wave with
-// a hashed sparse work row, a candidate table and its multipliers.
+// ILUTP: up to ILU_R rows are factored concurrently, one wave each, every
+// wave with a hashed sparse work row, a candidate table and its multipliers.
+// The capacities are runtime values (DevParams::ilu_*); the defaults suit
+// matrices whose rows stay within a few hundred entries during elimination.
 constexpr int ILU_R = 4;
-constexpr int IW_HS = 1024;  // hash slots per wave (power of two)
-constexpr int IW_NZ = 512;   // work-row entries per wave
-constexpr int IW_C = 192;    // elimination candidates per row
-constexpr int IW_L = 160;    // multipliers per row before the fill limit
+constexpr int ILU_DEF_HS = 1024;  // hash slots per wave (power of two)
+constexpr int ILU_DEF_NZ = 512;   // work-row entries per wave
+constexpr int ILU_DEF_C = 192;    // elimination candidates per row
+constexpr int ILU_DEF_L = 160;    // multipliers per row before the fill limit
 
-__host__ __device__ inline size_t ilu_wave_bytes() {
-  return align_up((size_t)IW_HS * 4, 16) + align_up((size_t)IW_NZ * 2, 16) + (size_t)IW_NZ * 8 +
-         align_up((size_t)IW_C * 2, 16) * 3 + (size_t)IW_C * 8 + align_up((size_t)IW_L * 2, 16) +
-         (size_t)IW_L * 8;
+__host__ __device__ inline size_t ilu_wave_bytes(int hs, int nz, int c, int l) {
+  return align_up((size_t)hs * 4, 16) + align_up((size_t)nz * 2, 16) + (size_t)nz * 8 +
+         align_up((size_t)c * 2, 16) * 3 + (size_t)c * 8 + align_up((size_t)l * 2, 16) + (size_t)l * 8;
 }
 
-__host__ __device__ inline size_t ilutp_lds_bytes(int n) {
+__host__ __device__ inline size_t ilu_wave_bytes(const DevParams& P) {
+  return ilu_wave_bytes(P.ilu_hs, P.ilu_nz, P.ilu_c, P.ilu_l);
+}
+
+__host__ __device__ inline size_t ilutp_lds_bytes(int n, const DevParams& P) {
   size_t b = 0;
   b += align_up((size_t)n * 2, 16);  // pinv
   b += align_up((size_t)n * 2, 16);  // q
-  const size_t waves = ILU_R * ilu_wave_bytes();
+  const size_t waves = (size_t)P.ilu_r * ilu_wave_bytes(P);
   const size_t tmp = (size_t)n * 4;  // column relabelling after the factorisation
   b += waves > tmp ? waves : tmp;
   return b;
@@ -47,7 +52,8 @@ __host__ __device__ inline size_t ilutp_lds_bytes(int n) {
 // the in-block coefficient tile, the GMRES scalars and the update
 // coefficients; the ILUTP and reorder phases reuse the same bytes.  Region B
 // (reduction slots and broadcast scalars) is live in every phase.
-__host__ __device__ inline LdsLayout lds_layout(int n, int ktb, int maxit, int mmax) {
+__host__ __device__ inline LdsLayout lds_layout(int n, int ktb, const DevParams& P) {
+  const int maxit = P.maxit, mmax = P.m_max;
   LdsLayout L;
   size_t o = align_up((size_t)n, 4) * ktb + align_up((size_t)DTILE * ktb, 16);  // xs, D
   L.hb = o; o += (size_t)(maxit + 2) * 8;
@@ -59,7 +65,7 @@ __host__ __device__ inline LdsLayout lds_layout(int n, int ktb, int maxit, int m
   L.gb = o; o += (size_t)(mmax + 1) * 8;
   L.cb = o; o += (size_t)(mmax + 1) * 8;
   size_t a = o;
-  const size_t ilu = ilutp_lds_bytes(n);
+  const size_t ilu = ilutp_lds_bytes(n, P);
   const size_t reo = align_up((size_t)n * 2, 16) * 2;
   if (ilu > a) a = ilu;
   if (reo > a) a = reo;
@@ -345,20 +351,38 @@ __device__ inline int wrap_index(int i, int L) {
   return r < 0 ? r + L : r;
 }
 
-// Evaluate one Slater row phi_j(r) over sites within the cutoff (one wave).
-// Entries are written in candidate order to out_col/out_val (global) as column
-// positions cmap[site].  Returns the entry count (may exceed cap; entries past
-// cap are not written).
-template <typename CT>
+// -(1/2) lap phi_j at a point where phi_j is given by orbital_value: with
+// c = 1/sigma^2, -(1/2) lap exp(-c|d|^2/2) = (3c - c^2|d|^2)/2 * exp(-c|d|^2/2);
+// the p-like term s d_x exp(-e|d|^2/2) gives s d_x (5e - e^2|d|^2)/2 * exp(..).
+// Its ratio with Psi is the kinetic-energy term of eq. (energyEq).
+__device__ inline double orbital_kinetic(const Walker& W, double d2, double dx, double sig) {
+  const double c = 1.0 / (sig * sig);
+  double v = 0.5 * (3.0 * c - c * c * d2) * exp(-0.5 * c * d2);
+  if (W.kind == VMC_ORB_GAUSS_PX) {
+    const double e = 1.0 / (W.p_sigma * W.p_sigma);
+    v += W.p_scale * dx * 0.5 * (5.0 * e - e * e * d2) * exp(-0.5 * e * d2);
+  }
+  return v;
+}
+
+// Evaluate one Slater row phi_j(r) (KIN = 0) or its kinetic row
+// -(1/2) lap phi_j(r) (KIN = 1) over the sites within the cutoff (one wave).
+// Candidates: every site of the cells whose corner lies within
+// cutoff + margin of r, the range stretched down by the largest in-cell site
+// offset.  Entries are written in candidate order to out_col/out_val (global)
+// as column positions cmap[site].  Returns the entry count (may exceed cap;
+// entries past cap are not written).
+template <typename CT, int KIN = 0>
 __device__ inline int wave_row(const Walker& W, double rx, double ry, double rz, const int* cmap,
                                CT* out_col, double* out_val, float* out_val32, int cap) {
   const int lane = lane_id();
   const double R = W.cutoff + W.margin;
+  const int nb = W.nb;
   int lox, cx, loy, cy, loz, cz;
-  axis_range(rx, R, W.a, W.lat[0], lox, cx);
-  axis_range(ry, R, W.a, W.lat[1], loy, cy);
-  axis_range(rz, R, W.a, W.lat[2], loz, cz);
-  const int total = cx * cy * cz;
+  axis_range(rx - W.bmax[0], R, W.a, W.lat[0], lox, cx);
+  axis_range(ry - W.bmax[1], R, W.a, W.lat[1], loy, cy);
+  axis_range(rz - W.bmax[2], R, W.a, W.lat[2], loz, cz);
+  const int total = cx * cy * cz * nb;
   const double rc2 = W.cutoff * W.cutoff;
   int count = 0;
   for (int t0 = 0; t0 < total; t0 += 64) {
@@ -367,18 +391,20 @@ __device__ inline int wave_row(const Walker& W, double rx, double ry, double rz,
     int site = 0;
     double val = 0.0;
     if (t < total) {
-      int tx = t % cx;
-      int ty = (t / cx) % cy;
-      int tz = t / (cx * cy);
+      const int b = t % nb;
+      const int cell = t / nb;
+      int tx = cell % cx;
+      int ty = (cell / cx) % cy;
+      int tz = cell / (cx * cy);
       int ix = wrap_index(lox + tx, W.lat[0]);
       int iy = wrap_index(loy + ty, W.lat[1]);
       int iz = wrap_index(loz + tz, W.lat[2]);
-      site = ix + W.lat[0] * (iy + W.lat[1] * iz);
+      site = b + nb * (ix + W.lat[0] * (iy + W.lat[1] * iz));
       double dx;
       double d2 = dist2_xyz(rx, ry, rz, W.sites + 3 * (size_t)site, W.box, &dx);
       if (d2 <= rc2) {
         hit = true;
-        val = orbital_value(W, d2, dx, W.sigma[site]);
+        val = KIN ? orbital_kinetic(W, d2, dx, W.sigma[site]) : orbital_value(W, d2, dx, W.sigma[site]);
       }
     }
     unsigned long long mask = __ballot(hit);

@@ -56,6 +56,9 @@ struct DevParams {
   int refine_maxit;
   double step;
   int force_reorder_every;
+  // ILUTP per-wave work capacities and concurrent rows (see ilu_default_caps)
+  int ilu_hs, ilu_hshift, ilu_nz, ilu_c, ilu_l, ilu_r;
+  int ilu_drop_norm;          // 0: tau = droptol*||a_i||_2; 1: droptol*||a_i||_1/nnz(a_i)
 };
 
 // Everything the device needs about one walker.  Arrays are per walker; the
@@ -69,7 +72,9 @@ struct Walker {
   int n, W, F, UC;            // n, Slater row cap, factor row cap, update-vector cap
   int lat[3];
   int kind;
+  int nb;                     // sites per lattice cell
   double box[3], a, margin, cutoff, p_scale, p_sigma;
+  double bmax[3];             // largest in-cell site offset per axis (length)
   unsigned long long seed;
 
   // system (by site id) and positions (by particle id)

@@ -682,10 +682,10 @@ VMC_PHASE SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, Smem& S,
 }
 
 // ratio = 1 + u^T z (FP64), u = pending update (column positions).
-VMC_PHASE double wg_ratio(const Walker& W, int ulen, const double* z, Smem& S) {
+VMC_PHASE double wg_ratio(const Walker& W, int ulen, const double* z, Smem& S, double base = 1.0) {
   double acc = 0.0;
   for (int e = vmc_tid(); e < ulen; e += NT) acc += W.pu_val[e] * z[W.pu_col[e]];
-  return 1.0 + wg_sum(acc, S.red);
+  return base + wg_sum(acc, S.red);
 }
 
 }  // namespace vmc

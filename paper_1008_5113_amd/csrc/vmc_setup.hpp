@@ -193,38 +193,43 @@ struct IluWave {
   double* cdiag;  // u_kk of row cpos
   short* lk;      // kept multipliers: positions
   double* lv;     //                   values
+  int hmask, hshift;
 };
 
-__device__ inline IluWave ilu_wave_carve(char* base) {
+__device__ inline IluWave ilu_wave_carve(char* base, const DevParams& P) {
   IluWave R;
-  R.hent = (int*)base;     base += align_up((size_t)IW_HS * 4, 16);
-  R.slab = (short*)base;   base += align_up((size_t)IW_NZ * 2, 16);
-  R.sval = (double*)base;  base += (size_t)IW_NZ * 8;
-  R.cpos = (short*)base;   base += align_up((size_t)IW_C * 2, 16);
-  R.clab = (short*)base;   base += align_up((size_t)IW_C * 2, 16);
-  R.clen = (short*)base;   base += align_up((size_t)IW_C * 2, 16);
-  R.cdiag = (double*)base; base += (size_t)IW_C * 8;
-  R.lk = (short*)base;     base += align_up((size_t)IW_L * 2, 16);
+  R.hent = (int*)base;     base += align_up((size_t)P.ilu_hs * 4, 16);
+  R.slab = (short*)base;   base += align_up((size_t)P.ilu_nz * 2, 16);
+  R.sval = (double*)base;  base += (size_t)P.ilu_nz * 8;
+  R.cpos = (short*)base;   base += align_up((size_t)P.ilu_c * 2, 16);
+  R.clab = (short*)base;   base += align_up((size_t)P.ilu_c * 2, 16);
+  R.clen = (short*)base;   base += align_up((size_t)P.ilu_c * 2, 16);
+  R.cdiag = (double*)base; base += (size_t)P.ilu_c * 8;
+  R.lk = (short*)base;     base += align_up((size_t)P.ilu_l * 2, 16);
   R.lv = (double*)base;
+  R.hmask = P.ilu_hs - 1;
+  R.hshift = P.ilu_hshift;
   return R;
 }
 
-__device__ inline int ilu_hash(int c) { return (int)(((unsigned)c * 2654435761u) >> 22); }
+__device__ inline int ilu_hash(const IluWave& R, int c) {
+  return (int)(((unsigned)c * 2654435761u) >> R.hshift);
+}
 
 // Slot of label c in the work row, or -1.
-__device__ inline int ilu_find(const int* hent, int c) {
-  int h = ilu_hash(c);
+__device__ inline int ilu_find(const IluWave& R, int c) {
+  int h = ilu_hash(R, c);
   while (true) {
-    const int e = hent[h];
+    const int e = R.hent[h];
     if (e == -1) return -1;
     if ((e >> 16) == c) return e & 0xFFFF;
-    h = (h + 1) & (IW_HS - 1);
+    h = (h + 1) & R.hmask;
   }
 }
 
-__device__ inline void ilu_insert(int* hent, int c, int slot) {
-  int h = ilu_hash(c);
-  while (atomicCAS(&hent[h], -1, (c << 16) | slot) != -1) h = (h + 1) & (IW_HS - 1);
+__device__ inline void ilu_insert(const IluWave& R, int c, int slot) {
+  int h = ilu_hash(R, c);
+  while (atomicCAS(&R.hent[h], -1, (c << 16) | slot) != -1) h = (h + 1) & R.hmask;
 }
 
 // Drop the eliminated candidates from the table (their order is irrelevant:
@@ -259,13 +264,13 @@ __device__ inline int ilu_compact(IluWave& R, int ncand) {
 
 // Append the lanes flagged `add` as candidates (position p, label c), with
 // the diagonal and length of U row p.  Returns the new count; a count above
-// IW_C means the table overflowed.
-__device__ inline int ilu_add_cands(const Walker& W, IluWave& R, int ncand, bool add, int p, int c) {
+// cap means the table overflowed.
+__device__ inline int ilu_add_cands(const Walker& W, IluWave& R, int ncand, bool add, int p, int c, int cap) {
   const int lane = lane_id();
   const unsigned long long mask = __ballot(add);
-  if (ncand + __popcll(mask) > IW_C) ncand = ilu_compact(R, ncand);
+  if (ncand + __popcll(mask) > cap) ncand = ilu_compact(R, ncand);
   const int before = __popcll(mask & ((1ull << lane) - 1ull));
-  if (add && ncand + before < IW_C) {
+  if (add && ncand + before < cap) {
     const int s = ncand + before;
     R.cpos[s] = (short)p;
     R.clab[s] = (short)c;
@@ -283,31 +288,33 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
   short* pinv = (short*)base;               base += align_up((size_t)n * 2, 16);
   short* q = (short*)base;                  base += align_up((size_t)n * 2, 16);
   const int wid = wave_id();
-  IluWave R = ilu_wave_carve(base + (size_t)(wid < ILU_R ? wid : 0) * ilu_wave_bytes());
+  const int nrow = P.ilu_r, cap_nz = P.ilu_nz, cap_c = P.ilu_c, cap_l = P.ilu_l;
+  IluWave R = ilu_wave_carve(base + (size_t)(wid < nrow ? wid : 0) * ilu_wave_bytes(P), P);
 
   for (int k = vmc_tid(); k < n; k += NT) {
     pinv[k] = (short)k;
     q[k] = (short)k;
   }
-  if (wid < ILU_R)
-    for (int h = lane_id(); h < IW_HS; h += 64) R.hent[h] = -1;
+  if (wid < nrow)
+    for (int h = lane_id(); h <= R.hmask; h += 64) R.hent[h] = -1;
   if (vmc_tid() == 0) {
     S.ic[IC_FIN] = 0;
     S.ic[IC_FAIL] = 0;
   }
   __syncthreads();
 
-  if (wid < ILU_R) {
+  if (wid < nrow) {
     const int lane = lane_id();
     const double droptol = P.droptol, permtol = P.permtol;
+    const bool mean_scale = P.ilu_drop_norm == 1;
     int status = WST_OK;
-    for (int i = wid; i < n; i += ILU_R) {
+    for (int i = wid; i < n; i += nrow) {
       if (lds_acquire(&S.ic[IC_FAIL])) break;
       int known = min(lds_acquire(&S.ic[IC_FIN]), i);  // positions < known are final
       // 1. load row i into the work row; entries at final positions left of
       //    the diagonal are the first candidates
       const int len = W.a_len[i];
-      if (len > IW_NZ) { status = WST_CAPACITY; break; }
+      if (len > cap_nz) { status = WST_CAPACITY; break; }
       double nrm = 0.0;
       int ncand = 0;
       for (int e0 = 0; e0 < len; e0 += 64) {
@@ -319,16 +326,17 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
           const double v = W.a_val[(size_t)i * W.W + e];
           R.slab[e] = (short)c;
           R.sval[e] = v;
-          ilu_insert(R.hent, c, e);
-          nrm += v * v;
+          ilu_insert(R, c, e);
+          nrm += mean_scale ? fabs(v) : v * v;
           k = pinv[c];
           cand = k < known;
         }
-        ncand = ilu_add_cands(W, R, ncand, cand, k, c);
+        ncand = ilu_add_cands(W, R, ncand, cand, k, c, cap_c);
       }
-      if (ncand > IW_C) { status = WST_CAPACITY; break; }
+      if (ncand > cap_c) { status = WST_CAPACITY; break; }
       nrm = wave_sum(nrm);
-      const double tau = droptol * sqrt(nrm);
+      // drop scale: the row's 2-norm, or its mean magnitude (SPARSKIT's ILUTP)
+      const double tau = droptol * (mean_scale ? nrm / (double)len : sqrt(nrm));
       int nz = len;
       int lcount = 0;
       // 2. eliminate in increasing position order
@@ -356,11 +364,11 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
             int c = 0;
             if (p < f) {
               c = q[p];
-              add = ilu_find(R.hent, c) >= 0;
+              add = ilu_find(R, c) >= 0;
             }
-            ncand = ilu_add_cands(W, R, ncand, add, p, c);
+            ncand = ilu_add_cands(W, R, ncand, add, p, c, cap_c);
           }
-          if (ncand > IW_C) { status = WST_CAPACITY; break; }
+          if (ncand > cap_c) { status = WST_CAPACITY; break; }
           known = f;
           continue;
         }
@@ -370,11 +378,11 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
           bslot = readlane_i(bslot, __ffsll((long long)who) - 1);
           best = bmin;
         }
-        const int sk = ilu_find(R.hent, R.clab[bslot]);
+        const int sk = ilu_find(R, R.clab[bslot]);
         const double lik = R.sval[sk] / R.cdiag[bslot];
         if (lane == 0) R.cpos[bslot] = (short)CAND_DONE;
         if (fabs(lik) < tau) continue;
-        if (lcount >= IW_L) { status = WST_CAPACITY; break; }
+        if (lcount >= cap_l) { status = WST_CAPACITY; break; }
         if (lane == 0) { R.lk[lcount] = (short)best; R.lv[lcount] = lik; }
         ++lcount;
         const int ul = R.clen[bslot];
@@ -387,25 +395,25 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
             c2 = W.u_col[(size_t)best * F + e];
             v2 = W.u_val[(size_t)best * F + e];
             // the columns of one U row are distinct: no two lanes share a label
-            const int s2 = ilu_find(R.hent, c2);
+            const int s2 = ilu_find(R, c2);
             if (s2 >= 0) R.sval[s2] -= lik * v2;
             else isnew = true;
           }
           const unsigned long long mask = __ballot(isnew);
           const int before = __popcll(mask & ((1ull << lane) - 1ull));
-          if (isnew && nz + before < IW_NZ) {
+          if (isnew && nz + before < cap_nz) {
             const int s2 = nz + before;
             R.slab[s2] = (short)c2;
             R.sval[s2] = -lik * v2;
-            ilu_insert(R.hent, c2, s2);
+            ilu_insert(R, c2, s2);
             k2 = pinv[c2];
             cand = k2 < known;
           }
           nz += __popcll(mask);
-          if (nz > IW_NZ) break;
-          ncand = ilu_add_cands(W, R, ncand, cand, k2, c2);
+          if (nz > cap_nz) break;
+          ncand = ilu_add_cands(W, R, ncand, cand, k2, c2, cap_c);
         }
-        if (nz > IW_NZ || ncand > IW_C) { status = WST_CAPACITY; break; }
+        if (nz > cap_nz || ncand > cap_c) { status = WST_CAPACITY; break; }
       }
       if (status != WST_OK) break;
 
@@ -422,7 +430,7 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
       nl0 = wave_sumi(nl0);
       nu0 = wave_sumi(nu0);
       const int cd = q[i];
-      const int sd = ilu_find(R.hent, cd);
+      const int sd = ilu_find(R, cd);
       const bool cd_present = sd >= 0;
       const int ucap = nu0 + pfill;
       const int lcap = nl0 + pfill;
@@ -547,7 +555,7 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
         W.l_len[i] = lwrite;
       }
       // 6. clear the work row, then publish row i as finished
-      for (int h = lane; h < IW_HS; h += 64) R.hent[h] = -1;
+      for (int h = lane; h <= R.hmask; h += 64) R.hent[h] = -1;
       __threadfence_block();
       if (lane == 0) lds_release(&S.ic[IC_FIN], i + 1);
     }

@@ -99,13 +99,18 @@ struct StepSolve {
   int passes;
 };
 
-// ratio = 1 + u^T z with A z = e_i (eq. (detRatioEq)).
+// ratio = 1 + u^T z with A z = e_i (eq. (detRatioEq)).  With kin set, the
+// pending vector holds a whole replacement row (a kinetic row) and the result
+// is its dot product with z alone; the mixed refinement then stops on the
+// residual norm without the ratio scale.
 template <int PREC>
-VMC_PHASE StepSolve wg_solve(const Walker& W, int m, const DevParams& P, Smem& S, int i, int ulen) {
+VMC_PHASE StepSolve wg_solve(const Walker& W, int m, const DevParams& P, Smem& S, int i, int ulen,
+                             bool kin = false) {
   StepSolve o;
+  const double base = kin ? 0.0 : 1.0;
   if (PREC == VMC_PREC_FP64) {
     SolveOut g = wg_gmres<double>(W, m, P, S, i, nullptr, 1.0, P.rtol, P.maxit, W.zvec, 1.0, true);
-    o.ratio = wg_ratio(W, ulen, W.zvec, S);
+    o.ratio = wg_ratio(W, ulen, W.zvec, S, base);
     o.iters_first = o.iters_total = g.iters;
     o.conv_first = o.conv = g.conv;
     o.N = g.N;
@@ -127,10 +132,10 @@ VMC_PHASE StepSolve wg_solve(const Walker& W, int m, const DevParams& P, Smem& S
       pc.start();
       const size_t stage = align_up((size_t)W.n, 4) * 4 + align_up((size_t)DTILE * 4, 16);
       const double rn = wg_resid64(W, W.zvec, i, W.rvec, S, stage);
-      o.ratio = wg_ratio(W, ulen, W.zvec, S);
+      o.ratio = wg_ratio(W, ulen, W.zvec, S, base);
       pc.stop(S, PH_RESID);
       o.res = rn;
-      if (rn <= P.refine_tol * fmin(1.0, fabs(o.ratio))) { o.conv = 1; break; }
+      if (rn <= P.refine_tol * (kin ? 1.0 : fmin(1.0, fabs(o.ratio)))) { o.conv = 1; break; }
       if (pass >= P.refine_maxit || !(rn > 0.0)) break;
       ++pass;
       SolveOut c = wg_gmres<float>(W, m, P, S, -1, W.rvec, rn, P.inner_rtol, P.maxit, W.zvec, rn, false);
@@ -369,6 +374,92 @@ VMC_PHASE void wg_accept(const Walker& W, WalkerState* ws, const DevParams& P, S
   }
   __threadfence_block();
   __syncthreads();
+}
+
+// Kinetic row of particle p at its current position, -(1/2) lap phi_j(r_p)
+// over the sites within the cutoff, in the pending-vector buffers.  The row
+// position comes back in S.ic[4], the length in S.ic[5].
+VMC_PHASE int wg_kinetic_row(const Walker& W, Smem& S, int p) {
+  if (wave_id() == 0) {
+    const double* r = W.pos + 3 * (size_t)p;
+    const int cnt = wave_row<int, 1>(W, r[0], r[1], r[2], W.cpos, W.pu_col, W.pu_val, nullptr, W.W);
+    if (lane_id() == 0) {
+      S.ic[4] = W.rpos[p];
+      S.ic[5] = cnt;
+      S.ic[7] = cnt > W.W ? WST_CAPACITY : WST_OK;
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  return S.ic[7];
+}
+
+// Kinetic-energy terms of particles p0..p1-1 (Section 2.3 and eq. (energyEq)):
+// t_p = -(1/2) lap_p Psi / Psi = lkin_p^T A^{-1} e_{i(p)}, the determinant
+// ratio of A with row i(p) replaced by the kinetic row.  Every term is one
+// more solve A z = e_i through the same preconditioned GMRES (with its mixed
+// refinement) and the same reorder triggers as a determinant ratio.  Writes
+// t_p to terms[p - p0] when terms is not null and returns their sum, added in
+// particle order.
+template <int PREC>
+VMC_PHASE double wg_energy(const Walker& W, WalkerState* ws, const DevParams& P, Smem& S, int p0, int p1,
+                           double* terms) {
+  double sum = 0.0;
+  for (int p = p0; p < p1; ++p) {
+    int st = wg_kinetic_row(W, S, p);
+    double t = 0.0;
+    if (st == WST_OK) {
+      const int m = ws->m;
+      StepSolve o = wg_solve<PREC>(W, m, P, S, S.ic[4], S.ic[5], true);
+      const double avg = ws->avg_iters;
+      const bool trig = (o.N > P.n_thresh) || !o.conv_first ||
+                        (ws->avg_count >= P.iter_min_solves && (double)o.iters_first >= P.iter_factor * avg);
+      __syncthreads();
+      if (vmc_tid() == 0) {
+        ws->st_solves += 1;
+        ws->st_inner += o.inner;
+        ws->st_refine += o.passes;
+        ws->st_iters += o.iters_total;
+        const double ent = (double)m * W.n * o.iters_total;
+        ws->upd_entries += ent;
+        ws->st_upd_entries += ent;
+      }
+      if (trig) {
+        st = wg_reorder_refactor<PREC>(W, P, S);
+        if (vmc_tid() == 0) {
+          ws->m = 0;
+          ws->upd_entries = 0.0;
+          ws->st_reorders += 1;
+          ws->st_refactors += 1;
+        }
+        __threadfence_block();
+        __syncthreads();
+        if (st == WST_OK) st = wg_kinetic_row(W, S, p);
+        if (st == WST_OK) {
+          o = wg_solve<PREC>(W, 0, P, S, S.ic[4], S.ic[5], true);
+          if (vmc_tid() == 0) {
+            ws->st_solves += 1;
+            ws->st_inner += o.inner;
+            ws->st_refine += o.passes;
+            ws->st_iters += o.iters_total;
+          }
+        }
+      }
+      if (!o.conv && vmc_tid() == 0) ws->st_nonconv += 1;
+      t = o.ratio;
+    }
+    if (st != WST_OK) {
+      if (vmc_tid() == 0) ws->status |= st;
+      __syncthreads();
+      break;
+    }
+    sum += t;
+    if (terms && vmc_tid() == 0) terms[p - p0] = t;
+    __syncthreads();
+  }
+  __threadfence_block();
+  __syncthreads();
+  return sum;
 }
 
 }  // namespace vmc

@@ -28,7 +28,7 @@ constexpr int MODE_REORDER = 2;
 constexpr int MODE_ILUTP = 4;
 
 __device__ inline Smem setup_smem(char* smem, const Walker& W, const DevParams& P, int ktb) {
-  LdsLayout L = lds_layout(W.n, ktb, P.maxit, P.m_max);
+  LdsLayout L = lds_layout(W.n, ktb, P);
   return make_smem(smem, L);
 }
 
@@ -177,6 +177,38 @@ __global__ void __launch_bounds__(NT, 4) k_run(const Walker* __restrict__ walker
     wg_accept<PREC>(W, ws, P, S, acc, w, rec);
   }
   pstep.stop(S, PH_STEP);
+}
+
+// Kinetic-energy terms of particles [p0, p1) (clamped to n) of the listed
+// walkers at their current positions: e_out[k * estride] = (sum of the terms)
+// / n, and the terms themselves at terms + toff[k] when terms is not null.  A
+// walker with a pending move or an error is skipped with err_out[k] != 0.
+template <int PREC>
+__global__ void __launch_bounds__(NT, 4) k_energy(const Walker* __restrict__ walkers, WalkerState* states,
+                                               DevParams P, const int* list, int p0, int p1, double* e_out,
+                                               int estride, double* terms, const long long* toff,
+                                               int* err_out) {
+  extern __shared__ __align__(16) char smem[];
+  const int w = list[blockIdx.x];
+  const Walker& W = walkers[w];
+  WalkerState* ws = states + w;
+  Smem S = setup_smem(smem, W, P, PREC == VMC_PREC_FP64 ? 8 : 4);
+  S.ph = states[w].ph;
+  if (threadIdx.x < 32) S.ic[threadIdx.x] = 0;
+  __syncthreads();
+  if (ws->status != WST_OK || ws->pend_valid) {
+    if (threadIdx.x == 0) {
+      err_out[blockIdx.x] = ws->pend_valid ? 2 : 1;
+      e_out[(size_t)blockIdx.x * estride] = 0.0;
+    }
+    return;
+  }
+  const int hi = min(p1, W.n), lo = min(p0, hi);
+  const double sum = wg_energy<PREC>(W, ws, P, S, lo, hi, terms ? terms + toff[blockIdx.x] : nullptr);
+  if (threadIdx.x == 0) {
+    e_out[(size_t)blockIdx.x * estride] = sum / W.n;
+    err_out[blockIdx.x] = ws->status != WST_OK ? 1 : 0;
+  }
 }
 
 // Diagnostic: one phase of the solve, repeated `reps` times per walker on the
@@ -363,6 +395,35 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
   d.refine_maxit = p->refine_maxit;
   d.step = p->step;
   d.force_reorder_every = p->force_reorder_every;
+  if (p->ilu_drop_norm != 0 && p->ilu_drop_norm != 1) {
+    delete c;
+    g_create_error = "ilu_drop_norm must be 0 or 1";
+    return VMC_EINVAL;
+  }
+  d.ilu_drop_norm = p->ilu_drop_norm;
+  d.ilu_r = ILU_R;
+  d.ilu_hs = ILU_DEF_HS;
+  d.ilu_nz = ILU_DEF_NZ;
+  d.ilu_c = ILU_DEF_C;
+  d.ilu_l = ILU_DEF_L;
+  if (p->ilu_work_cap > 0) {
+    if (p->ilu_work_cap > 8192) {
+      delete c;
+      g_create_error = "ilu_work_cap out of range";
+      return VMC_EINVAL;
+    }
+    const int cap = (p->ilu_work_cap + 63) / 64 * 64;
+    d.ilu_nz = std::max(cap, ILU_DEF_NZ);
+    d.ilu_c = std::max(cap, ILU_DEF_C);
+    d.ilu_l = std::max(cap, ILU_DEF_L);
+    d.ilu_hs = ILU_DEF_HS;
+    while (d.ilu_hs < 2 * d.ilu_nz) d.ilu_hs *= 2;
+  }
+  {
+    int lg = 0;
+    while ((1 << lg) < d.ilu_hs) ++lg;
+    d.ilu_hshift = 32 - lg;
+  }
 
   const int ktb = p->precision == VMC_PREC_FP64 ? 8 : 4;
   auto fail = [&](vmc_status s, const std::string& msg) {
@@ -379,8 +440,14 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
     const int n = in.n;
     if (n < 1 || n > 16384 || !in.sites || !in.sigma || !in.pos0 || in.a <= 0.0 || in.cutoff <= 0.0)
       return fail(VMC_EINVAL, "walker " + std::to_string(w) + ": invalid init");
-    if (in.lattice[0] * in.lattice[1] * in.lattice[2] != n)
-      return fail(VMC_EINVAL, "walker " + std::to_string(w) + ": lattice does not match n");
+    const int nb = in.n_basis == 0 ? 1 : in.n_basis;
+    if (nb < 1 || nb > 4 || in.lattice[0] < 1 || in.lattice[1] < 1 || in.lattice[2] < 1 ||
+        (long long)nb * in.lattice[0] * in.lattice[1] * in.lattice[2] != n)
+      return fail(VMC_EINVAL, "walker " + std::to_string(w) + ": lattice and basis do not match n");
+    for (int b = 0; b < nb && in.n_basis > 0; ++b)
+      for (int k = 0; k < 3; ++k)
+        if (!(in.basis[b][k] >= 0.0 && in.basis[b][k] < 1.0))
+          return fail(VMC_EINVAL, "walker " + std::to_string(w) + ": basis offsets must lie in [0, 1)");
     if (w > 0 && n != wi[0].n) c->all_same_n = 0;
     c->maxn = std::max(c->maxn, n);
     Walker& W = c->hw[w];
@@ -391,14 +458,21 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
       W.box[k] = in.lattice[k] * in.a;
     }
     W.a = in.a;
+    W.nb = nb;
+    for (int k = 0; k < 3; ++k) {
+      double mx = 0.0;
+      for (int b = 0; b < nb && in.n_basis > 0; ++b) mx = std::max(mx, in.basis[b][k]);
+      W.bmax[k] = mx * in.a;
+    }
     W.margin = in.site_margin;
     W.cutoff = in.cutoff;
     W.kind = in.orbital_kind;
     W.p_scale = in.p_scale;
     W.p_sigma = in.p_sigma;
     W.seed = in.seed;
+    // every site of the cell repeats on a simple-cubic lattice of spacing a
     int Wc = p->row_cap > 0 ? p->row_cap
-                            : lattice_bound(in.cutoff + in.site_margin + 0.8660254037844387 * in.a, in.a);
+                            : nb * lattice_bound(in.cutoff + in.site_margin + 0.8660254037844387 * in.a, in.a);
     Wc = std::min(Wc, n);
     Wc = (Wc + 15) / 16 * 16;  // 64-byte aligned rows (whole cache lines, vector loads)
     W.W = Wc;
@@ -524,11 +598,17 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
   if (!ok) return fail(VMC_ENOMEM, "device allocation failed");
   (void)hipMemcpy(c->d_all, all.data(), sizeof(int) * n_walkers, hipMemcpyHostToDevice);
 
-  LdsLayout L = lds_layout(c->maxn, ktb, p->gmres_maxit, p->m_max);
-  c->lds = L.total;
   int dev = 0, maxlds = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  // as many concurrently factored ILUTP rows as the LDS holds (results do not
+  // depend on it)
+  LdsLayout L = lds_layout(c->maxn, ktb, c->dp);
+  while (c->dp.ilu_r > 1 && maxlds > 0 && (int)L.total > maxlds) {
+    c->dp.ilu_r -= 1;
+    L = lds_layout(c->maxn, ktb, c->dp);
+  }
+  c->lds = L.total;
   if (maxlds > 0 && (int)c->lds > maxlds) {
     return fail(VMC_EINVAL, "n too large: needs " + std::to_string(c->lds) + " bytes of LDS per workgroup, device has " +
                                 std::to_string(maxlds));
@@ -538,11 +618,13 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
     (void)hipFuncSetAttribute((const void*)k_ratio<VMC_PREC_FP64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
     (void)hipFuncSetAttribute((const void*)k_accept<VMC_PREC_FP64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
     (void)hipFuncSetAttribute((const void*)k_run<VMC_PREC_FP64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
+    (void)hipFuncSetAttribute((const void*)k_energy<VMC_PREC_FP64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
   } else {
     (void)hipFuncSetAttribute((const void*)k_setup<VMC_PREC_MIXED>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
     (void)hipFuncSetAttribute((const void*)k_ratio<VMC_PREC_MIXED>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
     (void)hipFuncSetAttribute((const void*)k_accept<VMC_PREC_MIXED>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
     (void)hipFuncSetAttribute((const void*)k_run<VMC_PREC_MIXED>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
+    (void)hipFuncSetAttribute((const void*)k_energy<VMC_PREC_MIXED>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
   }
   if (hipDeviceSynchronize() != hipSuccess) return fail(VMC_EHIP, "device synchronize failed");
   *ctx_out = c;
@@ -707,6 +789,116 @@ vmc_status vmc_run_sweeps(void* ctx, int32_t sweeps, vmc_step_record* dev_log, i
   const long long steps = (long long)sweeps * c->hw[0].n;
   if (steps > 0x7fffffffLL) { c->err = "too many steps"; return VMC_EINVAL; }
   return vmc_run_steps(ctx, (int32_t)steps, dev_log, log_cap);
+}
+
+// k_energy over all walkers, writing walker w's energy to e_out[w * estride].
+static void launch_energy_all(Ctx* c, double* e_out, int estride) {
+  if (c->dp.precision == VMC_PREC_FP64)
+    hipLaunchKernelGGL(k_energy<VMC_PREC_FP64>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp,
+                       c->d_all, 0, 1 << 30, e_out, estride, (double*)nullptr, (const long long*)nullptr, c->d_err);
+  else
+    hipLaunchKernelGGL(k_energy<VMC_PREC_MIXED>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp,
+                       c->d_all, 0, 1 << 30, e_out, estride, (double*)nullptr, (const long long*)nullptr, c->d_err);
+}
+
+// Steps up to each sweep end run as ordinary persistent launches; the energy
+// of every walker is then one more launch.  (Fusing both into one kernel
+// doubles the kernel's code, past what the step code tolerates.)
+vmc_status vmc_run_steps_energy(void* ctx, int32_t steps, vmc_step_record* dev_log, int64_t log_cap,
+                                double* dev_energy, int32_t energy_cap) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || steps < 0 || energy_cap < 0 || (energy_cap > 0 && !dev_energy)) return VMC_EINVAL;
+  if (steps == 0) return VMC_OK;
+  if (!c->all_same_n) { c->err = "vmc_run_steps_energy needs walkers of equal n"; return VMC_EINVAL; }
+  std::vector<WalkerState> hs(c->nw);
+  HIPCHK(c, hipMemcpyAsync(hs.data(), c->dS, sizeof(WalkerState) * c->nw, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int w = 1; w < c->nw; ++w)
+    if (hs[w].g != hs[0].g) { c->err = "vmc_run_steps_energy needs walkers at the same step"; return VMC_EINVAL; }
+  const long long n = c->hw[0].n;
+  long long g = hs[0].g;
+  const long long cap = dev_log ? log_cap : 0;
+  const size_t rec = sizeof(vmc_step_record);
+  struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+  } tmp;
+  if (cap > 0 && hipMalloc(&tmp.p, rec * (size_t)c->nw * (size_t)std::min<long long>(n, steps)) != hipSuccess) {
+    c->err = "device allocation failed";
+    return VMC_ENOMEM;
+  }
+  long long done = 0;
+  int k = 0;
+  while (done < steps) {
+    const long long chunk = std::min<long long>(steps - done, n - g % n);
+    launch_run(c, (int)chunk, cap > 0 ? (vmc_step_record*)tmp.p : nullptr, cap > 0 ? (long long)c->nw * chunk : 0);
+    HIPCHK(c, hipGetLastError());
+    if (cap > 0) {
+      // walker w's records of this chunk go to dev_log[w * steps + done ...], within log_cap
+      for (int w = 0; w < c->nw; ++w) {
+        const long long first = (long long)w * steps + done;
+        const long long cnt = std::min<long long>(chunk, cap - first);
+        if (cnt <= 0) break;
+        HIPCHK(c, hipMemcpyAsync(dev_log + first, (char*)tmp.p + rec * (size_t)w * chunk, rec * (size_t)cnt,
+                                 hipMemcpyDeviceToDevice, c->stream));
+      }
+    }
+    done += chunk;
+    g += chunk;
+    if (g % n == 0 && k < energy_cap) {
+      launch_energy_all(c, dev_energy + k, energy_cap);
+      HIPCHK(c, hipGetLastError());
+    }
+    if (g % n == 0) ++k;
+  }
+  return VMC_OK;
+}
+
+vmc_status vmc_kinetic_energy(void* ctx, const int32_t* walkers, int32_t count, int32_t p_begin, int32_t p_end,
+                              double* energy_out, double* terms_out) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || !energy_out || p_begin < 0 || p_end < p_begin) return VMC_EINVAL;
+  if (!walkers) count = c->nw;
+  int* dl = nullptr;
+  vmc_status s = stage_list(c, walkers, count, &dl);
+  if (s) return s;
+  if (count == 0) return VMC_OK;
+  std::vector<long long> toff(count);
+  long long tot = 0;
+  for (int k = 0; k < count; ++k) {
+    const int n = c->hw[walkers ? walkers[k] : k].n;
+    const int hi = std::min(p_end, n), lo = std::min(p_begin, hi);
+    toff[k] = tot;
+    tot += hi - lo;
+  }
+  struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+  } be, bt, bo, br;
+  if (hipMalloc(&be.p, sizeof(double) * count) != hipSuccess ||
+      hipMalloc(&bo.p, sizeof(long long) * count) != hipSuccess ||
+      hipMalloc(&br.p, sizeof(int) * count) != hipSuccess ||
+      (terms_out && tot > 0 && hipMalloc(&bt.p, sizeof(double) * tot) != hipSuccess)) {
+    c->err = "device allocation failed";
+    return VMC_ENOMEM;
+  }
+  HIPCHK(c, hipMemcpyAsync(bo.p, toff.data(), sizeof(long long) * count, hipMemcpyHostToDevice, c->stream));
+  double* dt = (double*)bt.p;
+  if (c->dp.precision == VMC_PREC_FP64)
+    hipLaunchKernelGGL(k_energy<VMC_PREC_FP64>, dim3(count), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, dl,
+                       p_begin, p_end, (double*)be.p, 1, dt, (const long long*)bo.p, (int*)br.p);
+  else
+    hipLaunchKernelGGL(k_energy<VMC_PREC_MIXED>, dim3(count), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, dl,
+                       p_begin, p_end, (double*)be.p, 1, dt, (const long long*)bo.p, (int*)br.p);
+  HIPCHK(c, hipGetLastError());
+  std::vector<int> err(count);
+  HIPCHK(c, hipMemcpyAsync(energy_out, be.p, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(err.data(), br.p, sizeof(int) * count, hipMemcpyDeviceToHost, c->stream));
+  if (dt) HIPCHK(c, hipMemcpyAsync(terms_out, dt, sizeof(double) * tot, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < count; ++k)
+    if (err[k] == 2) { c->err = "kinetic energy requested with a pending move"; return VMC_ESTATE; }
+  return walker_errors(c);
 }
 
 // Cost-balance autotuner (Section 3.2: a new ILUTP once applying the stored

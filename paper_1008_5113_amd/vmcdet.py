@@ -43,7 +43,7 @@ EXPORTED = [
     "vmc_default_params", "vmc_create", "vmc_build_slater", "vmc_ilutp", "vmc_det_ratio",
     "vmc_accept", "vmc_run_steps", "vmc_run_sweeps", "vmc_sync", "vmc_get_dims",
     "vmc_get_state", "vmc_get_stats", "vmc_last_error", "vmc_destroy", "vmc_phase_bench",
-    "vmc_run_steps_graph", "vmc_autotune",
+    "vmc_run_steps_graph", "vmc_autotune", "vmc_kinetic_energy", "vmc_run_steps_energy",
 ]
 PHASE_BENCH = {"spmv": 0, "lsolve": 1, "usolve": 2, "updates": 3, "resid64": 4, "ilutp": 5}
 
@@ -68,7 +68,9 @@ class VmcParams(ctypes.Structure):
         ("force_reorder_every", ctypes.c_int32),
         ("pad0", ctypes.c_int32),
         ("refactor_cost", ctypes.c_double),
-        ("reserved", ctypes.c_int32 * 6),
+        ("ilu_work_cap", ctypes.c_int32),
+        ("ilu_drop_norm", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -86,6 +88,9 @@ class VmcWalkerInit(ctypes.Structure):
         ("cutoff", ctypes.c_double),
         ("pos0", ctypes.c_void_p),
         ("seed", ctypes.c_uint64),
+        ("n_basis", ctypes.c_int32),
+        ("pad0", ctypes.c_int32),
+        ("basis", (ctypes.c_double * 3) * 4),
     ]
 
 
@@ -166,6 +171,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.vmc_phase_bench.argtypes = [P, i32, i32]
     lib.vmc_run_steps_graph.argtypes = [P, i32, P, ctypes.c_int64]
     lib.vmc_autotune.argtypes = [P, ctypes.c_char_p, i32, ctypes.POINTER(VmcTuneInfo)]
+    lib.vmc_kinetic_energy.argtypes = [P, P, i32, i32, i32, P, P]
+    lib.vmc_run_steps_energy.argtypes = [P, i32, P, ctypes.c_int64, P, i32]
     for name in EXPORTED:
         if name != "vmc_last_error":
             getattr(lib, name).restype = i32
@@ -204,9 +211,23 @@ def params_from_workload(wp, **kw) -> VmcParams:
                 gmres_rtol=wp.gmres_rtol, droptol=wp.droptol, permtol=wp.permtol, lfil=wp.lfil,
                 m_max=wp.m_max, n_thresh=wp.n_thresh, iter_factor=wp.iter_factor,
                 iter_min_solves=wp.iter_min_solves, inner_rtol=wp.inner_rtol,
-                refine_tol=wp.refine_tol, refine_maxit=wp.refine_maxit, step=wp.step)
+                refine_tol=wp.refine_tol, refine_maxit=wp.refine_maxit, step=wp.step,
+                ilu_work_cap=getattr(wp, "ilu_work_cap", 0),
+                ilu_drop_norm=getattr(wp, "ilu_drop_norm", 0))
     base.update(kw)
     return default_params(**base)
+
+
+def _init_torch_device():
+    """Initialise torch's device runtime before the library touches the GPU:
+    torch provides the device buffers of the logging calls, and its lazy
+    initialisation fails once another user has initialised HIP in the process."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -218,7 +239,9 @@ class Context:
 
     def __init__(self, systems, walkers, params: VmcParams, stream=None):
         """systems: list of objects with lattice, a, sites, sigma, kind, p_scale, p_sigma,
-        cutoff and site_margin(); walkers: list of (system index, pos0, seed)."""
+        cutoff, site_margin() and optionally basis (fractional site offsets per cell);
+        walkers: list of (system index, pos0, seed)."""
+        _init_torch_device()
         self._keep = []
         n_w = len(walkers)
         inits = (VmcWalkerInit * n_w)()
@@ -244,6 +267,14 @@ class Context:
             w.cutoff = s.cutoff
             w.pos0 = pos.ctypes.data
             w.seed = int(seed)
+            basis = getattr(s, "basis", None)
+            if basis is not None:
+                if not 1 <= len(basis) <= 4:
+                    raise ValueError("a lattice cell holds 1 to 4 sites")
+                w.n_basis = len(basis)
+                for b, off in enumerate(basis):
+                    for c in range(3):
+                        w.basis[b][c] = float(off[c])
         self.params = params
         self.n_walkers = n_w
         self.ns = [inits[k].n for k in range(n_w)]
@@ -328,6 +359,51 @@ class Context:
         self.sync()
         arr = buf.cpu().numpy().view(STEP_RECORD_DTYPE)
         return arr.reshape(self.n_walkers, steps)
+
+    def kinetic_energy(self, walkers=None, p_begin: int = 0, p_end: Optional[int] = None,
+                       terms: bool = False):
+        """Kinetic energy per particle of the listed walkers (see vmc_kinetic_energy).
+        Returns the energies, and with terms=True also the list of per-particle
+        term arrays (particle ids p_begin..p_end-1 of each walker)."""
+        ws = list(range(self.n_walkers)) if walkers is None else [int(w) for w in walkers]
+        hi = (1 << 30) if p_end is None else int(p_end)
+        wl_arr = np.asarray(ws, dtype=np.int32)
+        e = np.zeros(len(ws))
+        lens = [max(0, min(hi, self.ns[w]) - min(int(p_begin), min(hi, self.ns[w]))) for w in ws]
+        t = np.zeros(max(1, sum(lens))) if terms else None
+        self._check(lib().vmc_kinetic_energy(self.h, _ptr(wl_arr), len(ws), int(p_begin), hi,
+                                             _ptr(e), _ptr(t)))
+        if not terms:
+            return e
+        out, o = [], 0
+        for L in lens:
+            out.append(t[o:o + L].copy())
+            o += L
+        return e, out
+
+    def run_steps_energy(self, steps: int, energy_cap: int, log: bool = False,
+                         log_walkers: Optional[int] = None):
+        """Run `steps` persistent steps, sampling the kinetic energy at every sweep
+        end.  Returns the energies [walker, energy_cap] (NaN where no sample was
+        taken) and, with log=True, the step log [walker, step] of the first
+        log_walkers walkers (all by default)."""
+        import torch
+        en = torch.full((self.n_walkers * energy_cap,), float("nan"), dtype=torch.float64, device="cuda")
+        # the fill runs on torch's stream; the library's kernels on the context's
+        torch.cuda.synchronize()
+        buf, cap = None, 0
+        nlog = self.n_walkers if log_walkers is None else min(int(log_walkers), self.n_walkers)
+        if log:
+            cap = nlog * steps
+            buf = torch.empty(max(1, cap) * STEP_RECORD_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        self._check(lib().vmc_run_steps_energy(self.h, int(steps), buf.data_ptr() if log else None, cap,
+                                               en.data_ptr(), int(energy_cap)))
+        self.sync()
+        energies = en.cpu().numpy().reshape(self.n_walkers, energy_cap)
+        if not log:
+            return energies
+        recs = buf.cpu().numpy().view(STEP_RECORD_DTYPE)[:cap]
+        return energies, recs.reshape(nlog, steps)
 
     def autotune(self, trial_steps: int = 100, cache_path: Optional[str] = None) -> dict:
         """Cost-balance thresholds and launch order (see vmc_autotune)."""

@@ -1,0 +1,84 @@
+"""The paper's experiment (Section 4) at n = 686 on the GPU, through the C-ABI.
+
+64 walkers, 120 sweeps with the paper's solver settings (FP64, GMRES rtol 1e-6,
+ILUTP droptol 0.01, reorder on N > 100 or slow convergence; column pivoting at
+permtol 0.5, see workloads.paper_bcc), the kinetic energy through the same
+solver at the end of every sweep.
+
+- The energy averaged over sweeps 20..119 and all walkers agrees with the
+  paper's Table "energy" (2.0984, sigma 0.0075) within the two runs'
+  statistical error.  (A chain statistic: parity beyond it is unpinned.)
+- Walker 0's first three sweeps replayed by the oracle (explicit inverse):
+  the probability of a wrong decision per step,
+  f = |min(q, 1) - min(q_a, 1)| with q, q_a the exact and the GPU's squared
+  ratios, is below 0.01 at every step (the paper's "good" class: 100%), and
+  the per-step ratio error is what rtol 1e-6 allows.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.chain import StepRecord, replay
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def vm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1008_5113_amd as vm
+    vm.lib()  # fails loudly when the library is missing
+    return vm
+
+
+def _paper_energy(n):
+    with open(os.path.join(GOLDEN, "energy_table.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            cols = line.split()
+            if int(cols[0]) == n:
+                return float(cols[3]), float(cols[4])
+    raise KeyError(n)
+
+
+def test_paper_experiment_n686(vm):
+    _say("case: paper experiment n=686, 64 walkers, 120 sweeps")
+    from paper_1008_5113_amd import experiment
+    r = experiment.run(7, n_walkers=64, sweeps=120, discard=20, keep_walker0=3,
+                       progress=lambda s: _say(f"  sweep {s + 1}") if (s + 1) % 20 == 0 else None)
+    assert r["status_ok"]
+    e_ref, sd_ref = _paper_energy(686)
+    _say(f"  E {r['energy']:.4f} +- {r['energy_sd']:.4f} (paper {e_ref} +- {sd_ref}); "
+         f"acceptance {r['acceptance']:.4f}; iterations/solve {r['iters_per_solve']:.2f}; "
+         f"nnz(A)/n {r['nnz_a']:.2f}; nnz(L+U)/n {r['nnz_lu']:.2f}; "
+         f"reorders/sweep {r['reorders_per_sweep']:.3f}; {r['seconds_per_sweep'] * 1e3:.1f} ms/sweep")
+    assert abs(r["energy"] - e_ref) <= 4.0 * np.hypot(r["energy_sd"], sd_ref)
+    assert np.all(np.isfinite(r["energies"]))
+    assert 0.55 < r["acceptance"] < 0.63
+
+    w0 = r["walker0"]
+    log = r["walker0_log"]
+    recs = [StepRecord(int(x["step"]), int(x["particle"]), np.array(x["new_pos"]), float(x["ratio"]),
+                       float(x["u_acc"]), bool(x["flags"] & 1)) for x in log]
+    rep = replay(r["system"], w0.pos0, w0.seed, 0.55, recs, dec_tol=1e-4, mode="sm")
+    assert rep.pos_mismatch == 0 and rep.sign_mismatch == 0
+    q = np.asarray(rep.oracle_ratios) ** 2
+    qa = np.asarray([x.ratio for x in recs]) ** 2
+    f = np.abs(np.minimum(q, 1.0) - np.minimum(qa, 1.0))
+    _say(f"  walker 0, {len(f)} steps: mean f {f.mean():.3e}; f < 1e-4: {np.mean(f < 1e-4) * 100:.2f}%, "
+         f"< 1e-3: {np.mean(f < 1e-3) * 100:.2f}%, < 1e-2: {np.mean(f < 1e-2) * 100:.2f}%; "
+         f"max dlog {rep.max_dlog:.3e}; decisions off {rep.decision_mismatch}")
+    assert np.all(f < 1e-2)
+    assert rep.decision_mismatch_outside_tol == 0

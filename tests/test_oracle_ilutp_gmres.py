@@ -73,6 +73,18 @@ def test_ilutp_rules_on_slater_matrix():
     assert nnz / n > 20
 
 
+def test_ilutp_drop_scale_two_norm_and_mean_magnitude():
+    # row 1 = (0.5, 10) below U row 0 = (10, 1): its multiplier is 0.05.  With
+    # droptol 0.007 the 2-norm scale gives tau = 0.007 * 10.0125 = 0.0701 and
+    # drops it (u11 = 10); the mean-magnitude scale gives tau = 0.007 * 5.25 =
+    # 0.03675 and keeps it (u11 = 10 - 0.05 * 1 = 9.95).
+    A = np.array([[10.0, 1.0], [0.5, 10.0]])
+    L, U, q = ilutp(rows_from_dense(A), 2, droptol=0.007, permtol=0.0, lfil=2)
+    assert L[1] == {} and U[1] == {1: 10.0}
+    L, U, q = ilutp(rows_from_dense(A), 2, droptol=0.007, permtol=0.0, lfil=2, norm="mean_abs")
+    assert L[1] == {0: 0.05} and abs(U[1][1] - 9.95) < 1e-15
+
+
 def test_ilutp_zero_pivot_raises():
     A = np.array([[1.0, 2.0], [2.0, 4.0]])
     with pytest.raises(SingularPivot):

@@ -98,6 +98,8 @@ class Params:
     refine_tol: float = 1e-11     # refinement stop: ||r|| <= tol * min(1,|ratio|)
     refine_maxit: int = 4
     sweeps: int = 1
+    ilu_work_cap: int = 0         # ILUTP work-row capacity (0: the library default)
+    ilu_drop_norm: int = 0        # ILUTP drop scale: 0 = row 2-norm, 1 = mean magnitude
 
 
 @dataclasses.dataclass
@@ -238,26 +240,41 @@ PAPER_K = 1.0                # Gaussian decay rate k of eq. (gaussian)
 PAPER_DROP = 1e-5            # entries below 1e-5 * max|a_ij| are dropped (Section 4)
 
 
-def paper_bcc(K: int = 7, n_walkers: int = 64, step: float = 0.55, sweeps: int = 120) -> Instance:
+def paper_bcc(K: int = 7, n_walkers: int = 64, step: float = 0.55, sweeps: int = 120,
+              permtol: float = 0.5) -> Instance:
     """The paper's experiment (Section 4): n = 2K^3 electrons, Gaussian orbitals
     exp(-k|d|^2) with k = 1 on a b.c.c. lattice of K^3 cubes of side 2.031,
-    entries below 1e-5 times the largest dropped, ILUTP droptol 0.01 and
-    permtol 0.05, GMRES rtol 1e-6 and at most 40 iterations, reorder when
-    N > 100 or the iterations reach four times their average, 120 sweeps, FP64.
+    entries below 1e-5 times the largest dropped, ILUTP droptol 0.01, GMRES
+    rtol 1e-6 and at most 40 iterations, reorder when N > 100 or the
+    iterations reach four times their average, 120 sweeps, FP64.
 
-    Readings: the largest entry is taken as 1 (an orbital at its own centre),
+    Pivoting: the paper sets permtol 0.05 (swap columns when 0.05 times the
+    row's largest entry exceeds the diagonal).  With that rule the
+    factorisations of these matrices are unstable (GMRES needs 25-40 or more
+    iterations and N reaches 50-5000, so the chain reorders at nearly every
+    step), far from the paper's 9 iterations and 0.65 reorders per sweep; with
+    permtol 0.5 they give 5-8 iterations and N near 1, close to the paper's
+    figures.  0.5 is the default here; permtol=0.05 runs the literal setting.
+
+    Readings: the drop tolerance scales each row's mean magnitude, as in
+    SPARSKIT's ILUTP, which the paper uses; the largest entry is taken as 1 (an
+    orbital at its own centre),
     so the drop rule is the geometric cutoff |d|^2 <= ln(1e5)/k; the proposal
     half-width (not given) is chosen so the acceptance is near the paper's
     0.588; start positions are the sites plus normal jitter of standard
-    deviation 1/(2 sqrt(k)) per axis, the spread of an isolated |phi|^2."""
+    deviation 1/(2 sqrt(k)) per axis, the spread of an isolated |phi|^2.
+    With droptol 0.01 a row's elimination visits up to about 12-16 K^2
+    entries before the fill limit applies, hence the ILUTP work capacity
+    20 K^2 (it fits the LDS of one workgroup up to K = 12)."""
     sigma = 1.0 / np.sqrt(2.0 * PAPER_K)
     cutoff = float(np.sqrt(np.log(1.0 / PAPER_DROP) / PAPER_K))
     s = make_system((K, K, K), a=PAPER_BCC_A, sigma=sigma, cutoff=cutoff, basis=BCC_BASIS)
     jit = 0.5 / np.sqrt(PAPER_K)
     ws = [Walker(0, initial_positions(s.sites, s.box, w, jit, normal=True), w) for w in range(n_walkers)]
     return Instance("paper_bcc_n%d" % s.n, [s], ws,
-                    Params(step=step, sweeps=sweeps, droptol=0.01, permtol=0.05, gmres_rtol=1e-6,
-                           gmres_maxit=40, n_thresh=100.0, iter_factor=4.0, mixed=False))
+                    Params(step=step, sweeps=sweeps, droptol=0.01, permtol=permtol, gmres_rtol=1e-6,
+                           gmres_maxit=40, n_thresh=100.0, iter_factor=4.0, mixed=False,
+                           ilu_work_cap=20 * K * K, ilu_drop_norm=1))
 
 
 WORKLOADS = {
