@@ -232,6 +232,56 @@ def phase_bench(inst, precision, walkers, stream_ptr, reps, warm_steps, **kw):
     return out
 
 
+def energy_bench(inst, walkers, stream_ptr, args):
+    """Kinetic-energy terms (Section 2.3, eq. (energyEq)) through the solver:
+    after the step warm-up (so the preconditioner carries stored updates),
+    one timed vmc_kinetic_energy call over particles [0, P) of every walker.
+    Each term is one more determinant-ratio solve."""
+    import torch
+    import paper_1008_5113_amd as vm
+    prec = vm.PREC_MIXED if inst.params.mixed else vm.PREC_FP64
+    kw = {"m_max": args.m_max} if args.m_max else {}
+    ctx = vm.Context.from_instance(inst, stream=stream_ptr, precision=prec, **kw)
+    ctx.ilutp(reorder=True)
+    tune = ctx.autotune(trial_steps=args.steps) if args.autotune else None
+    if args.warmup:
+        ctx.run_steps(args.warmup)
+    ctx.sync()
+    P = args.energy_particles
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0 = ctx.stats()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    energies = ctx.kinetic_energy(p_begin=0, p_end=P)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    s1 = ctx.stats()
+    ms = e0.elapsed_time(e1)
+    nnz = factor_nnz(ctx, list(range(min(4, len(walkers)))))
+    n = ctx.ns[0]
+    ctx.close()
+    bytes_ = algorithmic_bytes(s0, s1, nnz, n, prec == vm.PREC_MIXED)
+    d = lambda k: sum(b[k] - a[k] for a, b in zip(s0, s1))  # noqa: E731
+    terms = len(walkers) * P
+    gbs = bytes_ / (ms / 1e3) / 1e9
+    return {
+        "metric": "kinetic-energy terms per second (one GMRES solve each)",
+        "value": terms / (ms / 1e3), "unit": "terms/s", "n_gpus": 1, "ms": ms,
+        "higher_is_better": True, "dtype": "fp32+fp64" if prec == vm.PREC_MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": inst.name, "walkers": len(walkers), "n": n, "particles_per_walker": P,
+                   "warmup_steps": args.warmup, "autotune": bool(args.autotune)},
+        "iters_per_term": d("iters") / terms, "inner_per_term": d("inner_solves") / terms,
+        "refine_per_term": d("refine_passes") / terms, "reorders": d("reorders"),
+        "energy_partial_mean": float(np.mean(energies)),
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
+                     "frac": gbs / 8000.0, "traffic": None,
+                     "kernel": f"k_energy<{1 if prec == vm.PREC_MIXED else 0}>, one launch"},
+        "autotune_info": tune,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +303,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phases", action="store_true", help="per-phase micro-benchmarks only")
     ap.add_argument("--phase-reps", type=int, default=20)
+    ap.add_argument("--energy", action="store_true",
+                    help="time the kinetic energy through the solver instead of the step")
+    ap.add_argument("--energy-particles", type=int, default=128,
+                    help="particles per walker in the timed kinetic-energy call")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -285,6 +339,9 @@ def main():
     nw = len(inst.walkers)
     walkers = list(range(nw))
     stream_ptr = torch.cuda.current_stream().cuda_stream
+    if args.energy:
+        print(json.dumps(energy_bench(inst, walkers, stream_ptr, args)))
+        return
     if args.phases:
         res = {}
         for path in args.paths.split(","):

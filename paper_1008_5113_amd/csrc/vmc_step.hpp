@@ -420,6 +420,7 @@ VMC_PHASE double wg_energy(const Walker& W, WalkerState* ws, const DevParams& P,
         ws->st_inner += o.inner;
         ws->st_refine += o.passes;
         ws->st_iters += o.iters_total;
+        ws->st_msum += (long long)m * o.inner;
         const double ent = (double)m * W.n * o.iters_total;
         ws->upd_entries += ent;
         ws->st_upd_entries += ent;

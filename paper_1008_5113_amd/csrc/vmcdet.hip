@@ -509,7 +509,12 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
     size_t o_newcol = add((size_t)Wc * 4), o_newval = add((size_t)Wc * 8), o_pucol = add((size_t)W.UC * 4),
            o_puval = add((size_t)W.UC * 8);
     void* arena = nullptr;
-    if (hipMalloc(&arena, off) != hipSuccess) return fail(VMC_ENOMEM, "device allocation failed");
+    {
+      const hipError_t e = hipMalloc(&arena, off);
+      if (e != hipSuccess)
+        return fail(VMC_ENOMEM, "walker " + std::to_string(w) + ": device allocation of " + std::to_string(off) +
+                                    " bytes failed: " + hipGetErrorString(e));
+    }
     c->arenas.push_back(arena);
     if (hipMemset(arena, 0, off) != hipSuccess) return fail(VMC_EHIP, "memset failed");
     char* b = (char*)arena;
@@ -574,7 +579,7 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
   }
   if (hipMalloc(&c->dW, sizeof(Walker) * n_walkers) != hipSuccess ||
       hipMalloc(&c->dS, sizeof(WalkerState) * n_walkers) != hipSuccess)
-    return fail(VMC_ENOMEM, "device allocation failed");
+    return fail(VMC_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(hipGetLastError()));
   (void)hipMemcpy(c->dW, c->hw.data(), sizeof(Walker) * n_walkers, hipMemcpyHostToDevice);
   {
     std::vector<WalkerState> hs(n_walkers);
@@ -595,7 +600,7 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
   ok &= hipMalloc(&c->d_acc, n_walkers) == hipSuccess;
   ok &= hipMalloc(&c->d_err, sizeof(int) * n_walkers) == hipSuccess;
   ok &= hipMalloc(&c->d_order, sizeof(int) * n_walkers) == hipSuccess;
-  if (!ok) return fail(VMC_ENOMEM, "device allocation failed");
+  if (!ok) return fail(VMC_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(hipGetLastError()));
   (void)hipMemcpy(c->d_all, all.data(), sizeof(int) * n_walkers, hipMemcpyHostToDevice);
 
   int dev = 0, maxlds = 0;

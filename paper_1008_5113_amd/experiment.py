@@ -63,6 +63,7 @@ def run(K: int, n_walkers: int = 64, sweeps: int = 120, discard: int = 20, keep_
         ctx.ilutp(reorder=True)
         if autotune:
             ctx.autotune(trial_steps=n)
+        pos_start = ctx.state(0)["pos"] if keep_walker0 else None
         st0 = ctx.stats()
         energies = np.zeros((n_walkers, sweeps))
         acc = iters = reorders = steps = 0
@@ -111,6 +112,7 @@ def run(K: int, n_walkers: int = 64, sweeps: int = 120, discard: int = 20, keep_
     if keep_walker0:
         out["walker0_log"] = np.concatenate(kept)
         out["walker0"] = inst.walkers[0]
+        out["walker0_pos"] = pos_start   # positions where the kept records start
         out["system"] = inst.systems[0]
         out["energies"] = energies
     return out

@@ -149,6 +149,14 @@ class VmcTuneInfo(ctypes.Structure):
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"libvmcdet.so not built at {path}; run paper_1008_5113_amd/build.py")
+    # torch (which provides the device buffers of the logging calls) ships its
+    # own HIP runtime under the same soname.  Loading torch first makes the
+    # library bind to that one runtime; loaded the other way round, the process
+    # ends up with two runtimes and whichever initialises second finds no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     i32 = ctypes.c_int32
@@ -218,18 +226,6 @@ def params_from_workload(wp, **kw) -> VmcParams:
     return default_params(**base)
 
 
-def _init_torch_device():
-    """Initialise torch's device runtime before the library touches the GPU:
-    torch provides the device buffers of the logging calls, and its lazy
-    initialisation fails once another user has initialised HIP in the process."""
-    try:
-        import torch
-    except ImportError:
-        return
-    if torch.cuda.is_available():
-        torch.cuda.init()
-
-
 def _ptr(a: Optional[np.ndarray]):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
@@ -241,7 +237,6 @@ class Context:
         """systems: list of objects with lattice, a, sites, sigma, kind, p_scale, p_sigma,
         cutoff, site_margin() and optionally basis (fractional site offsets per cell);
         walkers: list of (system index, pos0, seed)."""
-        _init_torch_device()
         self._keep = []
         n_w = len(walkers)
         inits = (VmcWalkerInit * n_w)()
