@@ -24,8 +24,11 @@ COPY_BYTES = 1 << 30
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sources the step kernel is compiled from (its translation
+    unit: vmcdet.hip and the vmc_*.hpp headers it includes)."""
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+    files = [os.path.join(HERE, "csrc", "vmcdet.hip")] + glob.glob(os.path.join(HERE, "csrc", "vmc_*.hpp"))
+    for p in sorted(files):
         with open(p, "rb") as f:
             h.update(os.path.basename(p).encode())
             h.update(f.read())
