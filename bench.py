@@ -232,6 +232,33 @@ def phase_bench(inst, precision, walkers, stream_ptr, reps, warm_steps, **kw):
     return out
 
 
+def scaling_point(lattice, n_walkers, stream_ptr, args):
+    """Steps/s of both paths on an sc lattice of the n = 4000 workload's
+    orbitals (Gaussian 0.35 plus the p-like term, cutoff 2.5), beside the HBM
+    bound of the standard algorithm of Section 1 (explicit inverse, updated by
+    Sherman-Morrison on every accepted move).  An accepted move rewrites the
+    whole n x n FP64 inverse (read and write, 16 n^2 bytes); a rejected one
+    reads about (2W + 1) n entries; so at acceptance a the dense step moves
+    at least a 16 n^2 bytes and its rate is at most 8 TB/s / that."""
+    import workloads as wl
+    import paper_1008_5113_amd as vm
+    s = wl.make_system(lattice, sigma=0.35, kind=wl.ORB_GAUSS_PX, p_scale=0.1, p_sigma=0.5, cutoff=2.5)
+    ws = [wl.Walker(0, wl.initial_positions(s.sites, s.box, w, 0.3), w) for w in range(n_walkers)]
+    inst = wl.Instance(f"sc{lattice[0]}x{lattice[1]}x{lattice[2]}", [s], ws,
+                       wl.Params(step=0.25, mixed=True, m_max=96))
+    out = {"workload": inst.name, "n": s.n, "walkers": n_walkers}
+    walkers = list(range(n_walkers))
+    steps = args.steps
+    for path, prec in (("mixed", vm.PREC_MIXED), ("fp64", vm.PREC_FP64)):
+        r = run_path(inst, prec, steps, args.warmup, steps, walkers, stream_ptr,
+                     tune_steps=steps if args.autotune else 0, **({"m_max": args.m_max} if args.m_max else {}))
+        out[path] = {"steps_per_s": r["steps_per_s"], "accept": r["accept"], "iters_per_step": r["iters_per_step"],
+                     "alg_gbs": r["alg_gbs"]}
+    acc = out["fp64"]["accept"]
+    out["dense_standard_bound_steps_per_s"] = 8e12 / (acc * 16.0 * s.n * s.n)
+    return out
+
+
 def energy_bench(inst, walkers, stream_ptr, args):
     """Kinetic-energy terms (Section 2.3, eq. (energyEq)) through the solver:
     after the step warm-up (so the preconditioner carries stored updates),
@@ -307,6 +334,9 @@ def main():
                     help="time the kinetic energy through the solver instead of the step")
     ap.add_argument("--energy-particles", type=int, default=128,
                     help="particles per walker in the timed kinetic-energy call")
+    ap.add_argument("--scaling", default="",
+                    help="comma-separated sc lattices like 6x6x12,8x8x16: FP64 and mixed steps/s per n "
+                         "beside the HBM bound of the dense standard algorithm")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -341,6 +371,11 @@ def main():
     stream_ptr = torch.cuda.current_stream().cuda_stream
     if args.energy:
         print(json.dumps(energy_bench(inst, walkers, stream_ptr, args)))
+        return
+    if args.scaling:
+        for lat in args.scaling.split(","):
+            print(json.dumps(scaling_point(tuple(int(x) for x in lat.split("x")), nw, stream_ptr, args)),
+                  flush=True)
         return
     if args.phases:
         res = {}
