@@ -256,7 +256,40 @@ def scaling_point(lattice, n_walkers, stream_ptr, args):
                      "alg_gbs": r["alg_gbs"]}
     acc = out["fp64"]["accept"]
     out["dense_standard_bound_steps_per_s"] = 8e12 / (acc * 16.0 * s.n * s.n)
+    if args.dense_steps:
+        out["dense_standard"] = dense_standard(inst, walkers, stream_ptr, args.dense_steps)
     return out
+
+
+def dense_standard(inst, walkers, stream_ptr, steps):
+    """The standard algorithm on the GPU (explicit inverse, Sherman-Morrison on
+    accept): inverse built by the solver (untimed), one warm-up launch of 8
+    steps, then `steps` timed steps of every walker in one launch."""
+    import torch
+    import paper_1008_5113_amd as vm
+    ctx = vm.Context.from_instance(inst, walkers=walkers, precision=vm.PREC_FP64, stream=stream_ptr)
+    t0 = time.time()
+    ctx.ilutp(reorder=True)
+    ctx.sm_prepare(1e-12)
+    log(f"dense standard algorithm: inverses of {len(walkers)} walkers (n={ctx.ns[0]}) {time.time() - t0:.1f}s")
+    ctx.sm_run_steps(8)
+    s0 = ctx.stats()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    ctx.sm_run_steps(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    s1 = ctx.stats()
+    ms = e0.elapsed_time(e1)
+    ctx.close()
+    nsteps = sum(b["steps"] - a["steps"] for a, b in zip(s0, s1))
+    nacc = sum(b["accepted"] - a["accepted"] for a, b in zip(s0, s1))
+    n = inst.systems[0].n
+    bytes_ = nacc * 16.0 * n * n
+    return {"steps_per_s": nsteps / (ms / 1e3), "accept": nacc / max(1, nsteps),
+            "inverse_update_gbs": bytes_ / (ms / 1e3) / 1e9}
 
 
 def energy_bench(inst, walkers, stream_ptr, args):
@@ -337,6 +370,8 @@ def main():
     ap.add_argument("--scaling", default="",
                     help="comma-separated sc lattices like 6x6x12,8x8x16: FP64 and mixed steps/s per n "
                          "beside the HBM bound of the dense standard algorithm")
+    ap.add_argument("--dense-steps", type=int, default=100,
+                    help="with --scaling: timed steps of the GPU standard algorithm (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()

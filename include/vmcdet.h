@@ -270,6 +270,27 @@ vmc_status vmc_kinetic_energy(void* ctx, const int32_t* walkers, int32_t count, 
 vmc_status vmc_run_steps_energy(void* ctx, int32_t steps, vmc_step_record* dev_log, int64_t log_cap,
                                 double* dev_energy, int32_t energy_cap);
 
+/* The standard algorithm (Section 1), as a comparison path: the explicit
+   inverse of every walker's Slater matrix, read for each ratio and updated by
+   Sherman-Morrison on each accepted move, so an accepted step rewrites n^2
+   values.
+   vmc_sm_prepare allocates one n x n FP64 inverse per walker (8 n^2 bytes,
+   owned by the context) and fills it column by column with the
+   preconditioned solver at relative tolerance tol (e.g. 1e-13) from the
+   walkers' current state.  VMC_ENOCONV if a column misses tol, VMC_ESTATE with
+   a pending move.  Synchronous.
+   vmc_sm_run_steps then takes `steps` steps of every walker by the standard
+   algorithm: the same proposals, draws and decision rule as vmc_run_steps
+   (ratio = a'^T A^{-1} e_p), records in dev_log as vmc_run_steps writes them
+   (iters 0, N 0).  It moves the particles but leaves the sparse state (A, the
+   factors, the update list) behind: call vmc_build_slater and vmc_ilutp before
+   sparse steps again.  Asynchronous.
+   vmc_sm_get_inverse copies walker w's inverse to host_out (n*n doubles,
+   host_out[p*n + j] = (A^{-1})_{jp}, particle p, site j).  Synchronous. */
+vmc_status vmc_sm_prepare(void* ctx, double tol);
+vmc_status vmc_sm_run_steps(void* ctx, int32_t steps, vmc_step_record* dev_log, int64_t log_cap);
+vmc_status vmc_sm_get_inverse(void* ctx, int32_t walker, double* host_out);
+
 /* Autotuner for the batch (Section 3.2 cost balance, and the walker-to-
    workgroup map).  With a readable cache_path holding a threshold for every
    walker size n in the context, loads those; otherwise measures on the device:

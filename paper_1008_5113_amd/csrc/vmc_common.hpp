@@ -369,9 +369,9 @@ __device__ inline double orbital_kinetic(const Walker& W, double d2, double dx, 
 // -(1/2) lap phi_j(r) (KIN = 1) over the sites within the cutoff (one wave).
 // Candidates: every site of the cells whose corner lies within
 // cutoff + margin of r, the range stretched down by the largest in-cell site
-// offset.  Entries are written in candidate order to out_col/out_val (global)
-// as column positions cmap[site].  Returns the entry count (may exceed cap;
-// entries past cap are not written).
+// offset.  Entries are written in candidate order to out_col/out_val as
+// column positions cmap[site] (site ids when cmap is null).  Returns the entry
+// count (may exceed cap; entries past cap are not written).
 template <typename CT, int KIN = 0>
 __device__ inline int wave_row(const Walker& W, double rx, double ry, double rz, const int* cmap,
                                CT* out_col, double* out_val, float* out_val32, int cap) {
@@ -412,7 +412,7 @@ __device__ inline int wave_row(const Walker& W, double rx, double ry, double rz,
     if (hit) {
       int o = count + before;
       if (o < cap) {
-        out_col[o] = (CT)cmap[site];
+        out_col[o] = (CT)(cmap ? cmap[site] : site);
         out_val[o] = val;
         if (out_val32) out_val32[o] = (float)val;
       }

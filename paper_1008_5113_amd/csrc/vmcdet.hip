@@ -211,6 +211,188 @@ __global__ void __launch_bounds__(NT, 4) k_energy(const Walker* __restrict__ wal
   }
 }
 
+// ---------------------------------------------------------------------------
+// The standard algorithm (Section 1), as a comparison path: the explicit
+// inverse, read for the ratio and updated by Sherman-Morrison on an accepted
+// move.  Walker w's inverse is stored particle-major in original labels:
+// bmat[w][p * n + j] = (A^{-1})_{jp} for particle p and site j, so column p of
+// the inverse is one contiguous row.
+// ---------------------------------------------------------------------------
+
+// Row stride of a stored inverse (16-byte aligned rows) and the LDS carve of
+// the standard-algorithm step kernel.
+__host__ __device__ inline size_t sm_ld(int n) { return align_up((size_t)n, 2); }
+struct SmLds {
+  size_t col, nv, ov, nc, oc, sd, si, total;
+};
+__host__ __device__ inline SmLds sm_lds(int n, int cap) {
+  SmLds L;
+  size_t o = 0;
+  L.col = o; o += align_up((size_t)n * 8, 16);
+  L.nv = o;  o += align_up((size_t)cap * 8, 16);
+  L.ov = o;  o += align_up((size_t)cap * 8, 16);
+  L.nc = o;  o += align_up((size_t)cap * 4, 16);
+  L.oc = o;  o += align_up((size_t)cap * 4, 16);
+  L.sd = o;  o += 64;
+  L.si = o;  o += 32;
+  L.total = o;
+  return L;
+}
+
+// Columns p0..p1-1 of A^{-1}: A z = e_{rpos[p]} by the preconditioned solver
+// with its tolerance replaced by tol, z mapped back to site labels.
+template <int PREC>
+__global__ void __launch_bounds__(NT, 4) k_inverse_cols(const Walker* __restrict__ walkers, WalkerState* states,
+                                                     DevParams P, double* const* bmat, int p0, int p1,
+                                                     double tol, int* nonconv) {
+  extern __shared__ __align__(16) char smem[];
+  const int w = blockIdx.x;
+  const Walker& W = walkers[w];
+  WalkerState* ws = states + w;
+  P.rtol = tol;
+  P.refine_tol = tol;
+  Smem S = setup_smem(smem, W, P, PREC == VMC_PREC_FP64 ? 8 : 4);
+  if (threadIdx.x < 32) S.ic[threadIdx.x] = 0;
+  __syncthreads();
+  if (ws->status != WST_OK || ws->pend_valid) {
+    if (threadIdx.x == 0) nonconv[w] = -1;
+    return;
+  }
+  const int n = W.n;
+  const size_t ld = sm_ld(n);
+  double* B = bmat[w];
+  int bad = 0;
+  for (int p = p0; p < min(p1, n); ++p) {
+    const StepSolve o = wg_solve<PREC>(W, ws->m, P, S, W.rpos[p], 0, true);
+    bad += o.conv ? 0 : 1;
+    for (int c = vmc_tid(); c < n; c += NT) B[(size_t)p * ld + W.colsite[c]] = W.zvec[c];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) nonconv[w] = bad;
+}
+
+// `steps` Metropolis steps of every walker by the standard algorithm:
+// ratio = a'^T A^{-1} e_p; on accept A^{-1} <- A^{-1} - (A^{-1} e_p)(u^T A^{-1}) / ratio
+// with u = a' - a_p.  The proposal, the draws and the decision are those of
+// the sparse path.  Row m of the update is one wave's: it forms
+// (u^T A^{-1})_m from the row's entries at the two rows' sites, then streams
+// the row.  LDS: column p of the old inverse and the two Slater rows.
+__global__ void __launch_bounds__(NT) k_sm_run(const Walker* __restrict__ walkers, WalkerState* states,
+                                               DevParams P, double* const* bmat, int steps,
+                                               vmc_step_record* log, long long log_cap) {
+  extern __shared__ __align__(16) char smem[];
+  const int w = blockIdx.x;
+  const Walker& W = walkers[w];
+  WalkerState* ws = states + w;
+  const int n = W.n, cap = W.W;
+  const size_t ld = sm_ld(n);
+  const SmLds L = sm_lds(n, cap);
+  double* col = (double*)(smem + L.col);
+  double* nv = (double*)(smem + L.nv);
+  double* ov = (double*)(smem + L.ov);
+  int* nc = (int*)(smem + L.nc);
+  int* oc = (int*)(smem + L.oc);
+  double* sd = (double*)(smem + L.sd);  // [0] ratio
+  int* si = (int*)(smem + L.si);        // [0] new count, [1] old count
+  double* B = bmat[w];
+  const int lane = lane_id(), wid = wave_id();
+  for (int s = 0; s < steps; ++s) {
+    if (ws->status != WST_OK) break;
+    const long long g = ws->g;
+    double u[4];
+    step_draws(W.seed, g, u);
+    const int p = (int)(g % n);
+    double rnew[3], rold[3];
+    for (int c = 0; c < 3; ++c) {
+      rold[c] = W.pos[3 * p + c];
+      rnew[c] = propose_axis(rold[c], u[c], P.step, W.box[c]);
+    }
+    // new row (wave 0) and old row (wave 1), by site
+    if (wid == 0) {
+      const int cnt = wave_row<int, 0>(W, rnew[0], rnew[1], rnew[2], nullptr, nc, nv, nullptr, cap);
+      if (lane == 0) si[0] = cnt;
+    } else if (wid == 1) {
+      const int cnt = wave_row<int, 0>(W, rold[0], rold[1], rold[2], nullptr, oc, ov, nullptr, cap);
+      if (lane == 0) si[1] = cnt;
+    }
+    __syncthreads();
+    const int cn = si[0], co = si[1];
+    if (cn > cap || co > cap) {
+      if (threadIdx.x == 0) ws->status |= WST_CAPACITY;
+      break;
+    }
+    // ratio = a'^T (A^{-1} e_p) (wave 0), broadcast through LDS
+    if (wid == 0) {
+      double acc = 0.0;
+      for (int e = lane; e < cn; e += 64) acc += nv[e] * B[(size_t)p * ld + nc[e]];
+      acc = wave_sum(acc);
+      if (lane == 0) sd[0] = acc;
+    }
+    __syncthreads();
+    const double ratio = sd[0];
+    const int acc = (ratio * ratio > u[3]) ? 1 : 0;
+    if (acc) {
+      for (int j = vmc_tid(); j < n; j += NT) col[j] = B[(size_t)p * ld + j];
+      __syncthreads();
+      const double inv = 1.0 / ratio;
+      for (int m = wid; m < n; m += NWAVE) {
+        double* row = B + (size_t)m * ld;
+        double t = 0.0;
+        for (int e = lane; e < cn; e += 64) t += nv[e] * row[nc[e]];
+        for (int e = lane; e < co; e += 64) t -= ov[e] * row[oc[e]];
+        const double f = wave_sum(t) * inv;
+        int j = 2 * lane;
+        for (; j + 384 + 1 < n; j += 512) {
+          double2 x0 = *(const double2*)(row + j);
+          double2 x1 = *(const double2*)(row + j + 128);
+          double2 x2 = *(const double2*)(row + j + 256);
+          double2 x3 = *(const double2*)(row + j + 384);
+          x0.x -= f * col[j];       x0.y -= f * col[j + 1];
+          x1.x -= f * col[j + 128]; x1.y -= f * col[j + 129];
+          x2.x -= f * col[j + 256]; x2.y -= f * col[j + 257];
+          x3.x -= f * col[j + 384]; x3.y -= f * col[j + 385];
+          *(double2*)(row + j) = x0;
+          *(double2*)(row + j + 128) = x1;
+          *(double2*)(row + j + 256) = x2;
+          *(double2*)(row + j + 384) = x3;
+        }
+        for (; j < n; j += 128) {
+          row[j] -= f * col[j];
+          if (j + 1 < n) row[j + 1] -= f * col[j + 1];
+        }
+      }
+      if (threadIdx.x == 0) {
+        W.pos[3 * p] = rnew[0];
+        W.pos[3 * p + 1] = rnew[1];
+        W.pos[3 * p + 2] = rnew[2];
+      }
+    }
+    if (threadIdx.x == 0) {
+      const long long slot = (long long)w * steps + s;
+      if (log && slot < log_cap) {
+        vmc_step_record& r = log[slot];
+        r.step = g;
+        r.walker = w;
+        r.particle = p;
+        r.new_pos[0] = rnew[0];
+        r.new_pos[1] = rnew[1];
+        r.new_pos[2] = rnew[2];
+        r.ratio = ratio;
+        r.u_acc = u[3];
+        r.N = 0.0;
+        r.resid = 0.0;
+        r.iters = 0;
+        r.flags = (acc ? VMC_FLAG_ACCEPTED : 0) | VMC_FLAG_CONVERGED;
+      }
+      ws->g = g + 1;
+      ws->st_steps += 1;
+      if (acc) ws->st_acc += 1;
+    }
+    __threadfence();
+    __syncthreads();
+  }
+}
+
 // Diagnostic: one phase of the solve, repeated `reps` times per walker on the
 // walker's current matrix and factors (no state change except ILUTP).
 template <int PREC>
@@ -291,6 +473,11 @@ struct Ctx {
   void* g_log = nullptr;
   long long g_cap = -1;
   bool g_order = false;
+  // standard algorithm: one stored inverse per walker, and the device table of them
+  std::vector<void*> sm_bufs;
+  double** d_smB = nullptr;
+  int* d_nonconv = nullptr;
+  int max_cap = 0;
   std::string err;
 };
 
@@ -476,6 +663,7 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
     Wc = std::min(Wc, n);
     Wc = (Wc + 15) / 16 * 16;  // 64-byte aligned rows (whole cache lines, vector loads)
     W.W = Wc;
+    c->max_cap = std::max(c->max_cap, Wc);
     W.F = std::min(n, Wc + (Wc + 1) / 2 + 2);
     W.UC = 2 * Wc;
     const int km = p->gmres_maxit;
@@ -624,12 +812,14 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
     (void)hipFuncSetAttribute((const void*)k_accept<VMC_PREC_FP64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
     (void)hipFuncSetAttribute((const void*)k_run<VMC_PREC_FP64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
     (void)hipFuncSetAttribute((const void*)k_energy<VMC_PREC_FP64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
+    (void)hipFuncSetAttribute((const void*)k_inverse_cols<VMC_PREC_FP64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
   } else {
     (void)hipFuncSetAttribute((const void*)k_setup<VMC_PREC_MIXED>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
     (void)hipFuncSetAttribute((const void*)k_ratio<VMC_PREC_MIXED>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
     (void)hipFuncSetAttribute((const void*)k_accept<VMC_PREC_MIXED>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
     (void)hipFuncSetAttribute((const void*)k_run<VMC_PREC_MIXED>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
     (void)hipFuncSetAttribute((const void*)k_energy<VMC_PREC_MIXED>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
+    (void)hipFuncSetAttribute((const void*)k_inverse_cols<VMC_PREC_MIXED>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
   }
   if (hipDeviceSynchronize() != hipSuccess) return fail(VMC_EHIP, "device synchronize failed");
   *ctx_out = c;
@@ -906,6 +1096,76 @@ vmc_status vmc_kinetic_energy(void* ctx, const int32_t* walkers, int32_t count, 
   return walker_errors(c);
 }
 
+vmc_status vmc_sm_prepare(void* ctx, double tol) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || !(tol > 0.0)) return VMC_EINVAL;
+  if (!c->d_smB) {
+    std::vector<double*> ptrs(c->nw);
+    for (int w = 0; w < c->nw; ++w) {
+      void* b = nullptr;
+      const size_t bytes = sm_ld(c->hw[w].n) * (size_t)c->hw[w].n * 8;
+      const hipError_t e = hipMalloc(&b, bytes);
+      if (e != hipSuccess) {
+        for (void* q : c->sm_bufs) (void)hipFree(q);
+        c->sm_bufs.clear();
+        c->err = "walker " + std::to_string(w) + ": allocation of the " + std::to_string(bytes) +
+                 "-byte inverse failed: " + hipGetErrorString(e);
+        return VMC_ENOMEM;
+      }
+      c->sm_bufs.push_back(b);
+      ptrs[w] = (double*)b;
+    }
+    if (hipMalloc(&c->d_smB, sizeof(double*) * c->nw) != hipSuccess ||
+        hipMalloc(&c->d_nonconv, sizeof(int) * c->nw) != hipSuccess) {
+      c->err = "device allocation failed";
+      return VMC_ENOMEM;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_smB, ptrs.data(), sizeof(double*) * c->nw, hipMemcpyHostToDevice, c->stream));
+  }
+  if (c->dp.precision == VMC_PREC_FP64)
+    hipLaunchKernelGGL(k_inverse_cols<VMC_PREC_FP64>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp,
+                       (double* const*)c->d_smB, 0, c->maxn, tol, c->d_nonconv);
+  else
+    hipLaunchKernelGGL(k_inverse_cols<VMC_PREC_MIXED>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp,
+                       (double* const*)c->d_smB, 0, c->maxn, tol, c->d_nonconv);
+  HIPCHK(c, hipGetLastError());
+  std::vector<int> bad(c->nw);
+  HIPCHK(c, hipMemcpyAsync(bad.data(), c->d_nonconv, sizeof(int) * c->nw, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int w = 0; w < c->nw; ++w) {
+    if (bad[w] < 0) { c->err = "walker " + std::to_string(w) + ": pending move or error"; return VMC_ESTATE; }
+    if (bad[w] > 0) {
+      c->err = "walker " + std::to_string(w) + ": " + std::to_string(bad[w]) + " inverse columns missed the tolerance";
+      return VMC_ENOCONV;
+    }
+  }
+  return walker_errors(c);
+}
+
+vmc_status vmc_sm_run_steps(void* ctx, int32_t steps, vmc_step_record* dev_log, int64_t log_cap) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || steps < 0) return VMC_EINVAL;
+  if (!c->d_smB) { c->err = "vmc_sm_run_steps before vmc_sm_prepare"; return VMC_ESTATE; }
+  if (steps == 0) return VMC_OK;
+  const size_t lds = sm_lds(c->maxn, c->max_cap).total;
+  (void)hipFuncSetAttribute((const void*)k_sm_run, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k_sm_run, dim3(c->nw), dim3(NT), lds, c->stream, c->dW, c->dS, c->dp, (double* const*)c->d_smB,
+                     steps, dev_log, (long long)(dev_log ? log_cap : 0));
+  HIPCHK(c, hipGetLastError());
+  return VMC_OK;
+}
+
+vmc_status vmc_sm_get_inverse(void* ctx, int32_t walker, double* host_out) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || !host_out || walker < 0 || walker >= c->nw) return VMC_EINVAL;
+  if (!c->d_smB) { c->err = "no stored inverse (call vmc_sm_prepare)"; return VMC_ESTATE; }
+  const int n = c->hw[walker].n;
+  HIPCHK(c, hipMemcpy2DAsync(host_out, (size_t)n * 8, c->sm_bufs[walker], sm_ld(n) * 8, (size_t)n * 8, n,
+                             hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return VMC_OK;
+}
+
 // Cost-balance autotuner (Section 3.2: a new ILUTP once applying the stored
 // updates has cost as much as computing it), plus the longest-first launch
 // order of the walkers.  Per walker size n the thresholds are medians, so a
@@ -1141,6 +1401,9 @@ vmc_status vmc_destroy(void* ctx) {
   (void)hipFree(c->d_order);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
+  for (void* b : c->sm_bufs) (void)hipFree(b);
+  if (c->d_smB) (void)hipFree(c->d_smB);
+  if (c->d_nonconv) (void)hipFree(c->d_nonconv);
   delete c;
   return VMC_OK;
 }

@@ -44,6 +44,7 @@ EXPORTED = [
     "vmc_accept", "vmc_run_steps", "vmc_run_sweeps", "vmc_sync", "vmc_get_dims",
     "vmc_get_state", "vmc_get_stats", "vmc_last_error", "vmc_destroy", "vmc_phase_bench",
     "vmc_run_steps_graph", "vmc_autotune", "vmc_kinetic_energy", "vmc_run_steps_energy",
+    "vmc_sm_prepare", "vmc_sm_run_steps", "vmc_sm_get_inverse",
 ]
 PHASE_BENCH = {"spmv": 0, "lsolve": 1, "usolve": 2, "updates": 3, "resid64": 4, "ilutp": 5}
 
@@ -181,6 +182,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.vmc_autotune.argtypes = [P, ctypes.c_char_p, i32, ctypes.POINTER(VmcTuneInfo)]
     lib.vmc_kinetic_energy.argtypes = [P, P, i32, i32, i32, P, P]
     lib.vmc_run_steps_energy.argtypes = [P, i32, P, ctypes.c_int64, P, i32]
+    lib.vmc_sm_prepare.argtypes = [P, ctypes.c_double]
+    lib.vmc_sm_run_steps.argtypes = [P, i32, P, ctypes.c_int64]
+    lib.vmc_sm_get_inverse.argtypes = [P, i32, P]
     for name in EXPORTED:
         if name != "vmc_last_error":
             getattr(lib, name).restype = i32
@@ -399,6 +403,30 @@ class Context:
             return energies
         recs = buf.cpu().numpy().view(STEP_RECORD_DTYPE)[:cap]
         return energies, recs.reshape(nlog, steps)
+
+    def sm_prepare(self, tol: float = 1e-13):
+        """Explicit inverses for the standard algorithm (see vmc_sm_prepare)."""
+        self._check(lib().vmc_sm_prepare(self.h, float(tol)))
+
+    def sm_run_steps(self, steps: int, log: bool = False):
+        """Steps by the standard algorithm; with log=True returns the step log
+        [walker, step]."""
+        import torch
+        if not log:
+            self._check(lib().vmc_sm_run_steps(self.h, int(steps), None, 0))
+            return None
+        cap = self.n_walkers * steps
+        buf = torch.empty(cap * STEP_RECORD_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        self._check(lib().vmc_sm_run_steps(self.h, int(steps), buf.data_ptr(), cap))
+        self.sync()
+        return buf.cpu().numpy().view(STEP_RECORD_DTYPE).reshape(self.n_walkers, steps)
+
+    def sm_inverse(self, walker: int) -> np.ndarray:
+        """Walker's stored inverse as B[j, p] = (A^{-1})_{jp} (site j, particle p)."""
+        n = self.ns[walker]
+        out = np.zeros((n, n))
+        self._check(lib().vmc_sm_get_inverse(self.h, int(walker), _ptr(out)))
+        return out.T.copy()
 
     def autotune(self, trial_steps: int = 100, cache_path: Optional[str] = None) -> dict:
         """Cost-balance thresholds and launch order (see vmc_autotune)."""
