@@ -1,11 +1,11 @@
 """The paper's experiment (Section 4) at n = 686 on the GPU, through the C-ABI.
 
-128 walkers, 50 sweeps with the paper's solver settings (FP64, GMRES rtol
+128 walkers, 40 sweeps with the paper's solver settings (FP64, GMRES rtol
 1e-6, ILUTP droptol 0.01, reorder on N > 100 or slow convergence; column
 pivoting at permtol 0.5, see workloads.paper_bcc; refactor period by the cost
 balance), the kinetic energy through the same solver at the end of every sweep.
 
-- The energy averaged over sweeps 20..49 and all walkers agrees with the
+- The energy averaged over sweeps 20..39 and all walkers agrees with the
   paper's Table "energy" (2.0984, sigma 0.0075) within the two runs'
   statistical error (ours from the spread of the walkers' means; the paper
   discards 20 sweeps too).  A chain statistic: parity beyond it is unpinned.
@@ -55,9 +55,9 @@ def _paper_energy(n):
 
 
 def test_paper_experiment_n686(vm):
-    _say("case: paper experiment n=686, 128 walkers, 50 sweeps")
+    _say("case: paper experiment n=686, 128 walkers, 40 sweeps")
     from paper_1008_5113_amd import experiment
-    r = experiment.run(7, n_walkers=128, sweeps=50, discard=20, keep_walker0=3,
+    r = experiment.run(7, n_walkers=128, sweeps=40, discard=20, keep_walker0=3,
                        progress=lambda s: _say(f"  sweep {s + 1}") if (s + 1) % 10 == 0 else None)
     assert r["status_ok"]
     e_ref, sd_ref = _paper_energy(686)
