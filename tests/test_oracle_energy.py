@@ -135,3 +135,12 @@ def test_chain_energy_matches_paper_table():
     tol = 4.0 * np.hypot(sig_ours, sig_ref)
     assert abs(tail.mean() - e_ref) <= tol, (tail.mean(), sig_ours)
     assert 0.5 < acc / (50 * s.n) < 0.7
+
+
+def test_experiment_tables_match_golden():
+    """The experiment runner's copy of the paper's energy table is the golden one."""
+    from paper_1008_5113_amd.experiment import PAPER_TABLES
+    table = _paper_table()
+    assert sorted(PAPER_TABLES) == sorted(table)
+    for n, (es, ss, ep, sp) in table.items():
+        assert PAPER_TABLES[n]["energy"] == ep and PAPER_TABLES[n]["energy_sd"] == sp
