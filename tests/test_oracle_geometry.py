@@ -84,3 +84,21 @@ def test_propose_exact_arithmetic():
             x += box[c]
         assert out[c] == x
         assert 0.0 <= out[c] < box[c]
+
+
+def test_paper_bcc_lattice_matches_section4():
+    """Section 4: cube side 2.031, nearest-neighbour distance 1.759, density
+    3/(4 pi) = 0.2387 electrons per unit volume, n = 2 K^3; entries below 1e-5
+    of the largest (1) are dropped."""
+    from oracle.geometry import dist2
+    for K in (4, 7):
+        s = wl.paper_bcc(K=K, n_walkers=1).systems[0]
+        assert s.n == 2 * K ** 3
+        vol = float(np.prod(s.box))
+        assert abs(s.n / vol - 3.0 / (4.0 * np.pi)) < 5e-5
+        d = np.sqrt(dist2(s.sites[0][None, :], s.sites[1:], s.box))
+        assert abs(d.min() - 1.759) < 5e-4
+        assert np.sum(np.abs(d - d.min()) < 1e-12) == 8          # b.c.c. coordination
+        k = 1.0 / (2.0 * s.sigma[0] ** 2)
+        assert abs(k - 1.0) < 1e-15
+        assert abs(np.exp(-k * s.cutoff ** 2) - 1e-5) < 1e-18
