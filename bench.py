@@ -301,6 +301,8 @@ def energy_bench(inst, walkers, stream_ptr, args):
     import paper_1008_5113_amd as vm
     prec = vm.PREC_MIXED if inst.params.mixed else vm.PREC_FP64
     kw = {"m_max": args.m_max} if args.m_max else {}
+    if args.energy_tol > 0:
+        kw["energy_tol"] = args.energy_tol
     ctx = vm.Context.from_instance(inst, stream=stream_ptr, precision=prec, **kw)
     ctx.ilutp(reorder=True)
     tune = ctx.autotune(trial_steps=args.steps) if args.autotune else None
@@ -331,7 +333,8 @@ def energy_bench(inst, walkers, stream_ptr, args):
         "higher_is_better": True, "dtype": "fp32+fp64" if prec == vm.PREC_MIXED else "f64",
         "data": "synthetic",
         "config": {"workload": inst.name, "walkers": len(walkers), "n": n, "particles_per_walker": P,
-                   "warmup_steps": args.warmup, "autotune": bool(args.autotune)},
+                   "warmup_steps": args.warmup, "autotune": bool(args.autotune),
+                   "energy_tol": args.energy_tol if args.energy_tol > 0 else "ratio solves'"},
         "iters_per_term": d("iters") / terms, "inner_per_term": d("inner_solves") / terms,
         "refine_per_term": d("refine_passes") / terms, "reorders": d("reorders"),
         "energy_partial_mean": float(np.mean(energies)),
@@ -367,6 +370,8 @@ def main():
                     help="time the kinetic energy through the solver instead of the step")
     ap.add_argument("--energy-particles", type=int, default=128,
                     help="particles per walker in the timed kinetic-energy call")
+    ap.add_argument("--energy-tol", type=float, default=0.0,
+                    help="residual tolerance of the kinetic-energy solves (0: the ratio solves')")
     ap.add_argument("--scaling", default="",
                     help="comma-separated sc lattices like 6x6x12,8x8x16: FP64 and mixed steps/s per n "
                          "beside the HBM bound of the dense standard algorithm")

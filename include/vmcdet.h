@@ -100,7 +100,11 @@ typedef struct vmc_params {
   int32_t ilu_drop_norm;    /* ILUTP drop scale of row i: 0 = droptol * ||a_i||_2; 1 =
                                droptol * ||a_i||_1 / nnz(a_i), the mean magnitude that
                                SPARSKIT's ILUTP (the paper's preconditioner, Section 4) uses */
-  int32_t reserved[4];
+  double energy_tol;        /* residual at which the kinetic-energy solves stop (the FP64
+                               path's GMRES rtol and the mixed path's refinement tolerance);
+                               <= 0: the tolerances of the ratio solves.  A term then errs by
+                               at most ||A^{-T} lkin_p|| * energy_tol */
+  int32_t reserved[2];
 } vmc_params;
 
 /* One walker: its physical system (orbital centres and shapes) and start. */

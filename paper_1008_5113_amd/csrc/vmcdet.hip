@@ -986,13 +986,25 @@ vmc_status vmc_run_sweeps(void* ctx, int32_t sweeps, vmc_step_record* dev_log, i
   return vmc_run_steps(ctx, (int32_t)steps, dev_log, log_cap);
 }
 
+// Solver parameters of the kinetic-energy solves: the ratio solves' unless
+// energy_tol is set.
+static DevParams energy_params(const Ctx* c) {
+  DevParams d = c->dp;
+  if (c->prm.energy_tol > 0.0) {
+    d.rtol = c->prm.energy_tol;
+    d.refine_tol = c->prm.energy_tol;
+  }
+  return d;
+}
+
 // k_energy over all walkers, writing walker w's energy to e_out[w * estride].
 static void launch_energy_all(Ctx* c, double* e_out, int estride) {
+  const DevParams d = energy_params(c);
   if (c->dp.precision == VMC_PREC_FP64)
-    hipLaunchKernelGGL(k_energy<VMC_PREC_FP64>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp,
+    hipLaunchKernelGGL(k_energy<VMC_PREC_FP64>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, d,
                        c->d_all, 0, 1 << 30, e_out, estride, (double*)nullptr, (const long long*)nullptr, c->d_err);
   else
-    hipLaunchKernelGGL(k_energy<VMC_PREC_MIXED>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp,
+    hipLaunchKernelGGL(k_energy<VMC_PREC_MIXED>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, d,
                        c->d_all, 0, 1 << 30, e_out, estride, (double*)nullptr, (const long long*)nullptr, c->d_err);
 }
 
@@ -1079,11 +1091,12 @@ vmc_status vmc_kinetic_energy(void* ctx, const int32_t* walkers, int32_t count, 
   }
   HIPCHK(c, hipMemcpyAsync(bo.p, toff.data(), sizeof(long long) * count, hipMemcpyHostToDevice, c->stream));
   double* dt = (double*)bt.p;
+  const DevParams dpe = energy_params(c);
   if (c->dp.precision == VMC_PREC_FP64)
-    hipLaunchKernelGGL(k_energy<VMC_PREC_FP64>, dim3(count), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, dl,
+    hipLaunchKernelGGL(k_energy<VMC_PREC_FP64>, dim3(count), dim3(NT), c->lds, c->stream, c->dW, c->dS, dpe, dl,
                        p_begin, p_end, (double*)be.p, 1, dt, (const long long*)bo.p, (int*)br.p);
   else
-    hipLaunchKernelGGL(k_energy<VMC_PREC_MIXED>, dim3(count), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, dl,
+    hipLaunchKernelGGL(k_energy<VMC_PREC_MIXED>, dim3(count), dim3(NT), c->lds, c->stream, c->dW, c->dS, dpe, dl,
                        p_begin, p_end, (double*)be.p, 1, dt, (const long long*)bo.p, (int*)br.p);
   HIPCHK(c, hipGetLastError());
   std::vector<int> err(count);

@@ -71,7 +71,8 @@ class VmcParams(ctypes.Structure):
         ("refactor_cost", ctypes.c_double),
         ("ilu_work_cap", ctypes.c_int32),
         ("ilu_drop_norm", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("energy_tol", ctypes.c_double),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 

@@ -130,6 +130,35 @@ def test_kinetic_terms_vs_oracle(vm, case):
     assert abs(e[0] - ref.mean()) <= bound.mean()
 
 
+@pytest.mark.parametrize("case", ["plain_n128_fp64", "px_n640_mixed"])
+def test_kinetic_terms_loose_tolerance(vm, case):
+    """energy_tol = 1e-6 (the paper's GMRES tolerance): every term within the
+    residual bound at that tolerance, and fewer iterations than at the ratio
+    solves' tolerance."""
+    _say(f"case: kinetic terms at energy_tol 1e-6, {case}")
+    inst = CASES[case]()
+    s = inst.systems[0]
+    out = {}
+    for tol in (0.0, 1e-6):
+        ctx = vm.Context.from_instance(inst, energy_tol=tol)
+        ctx.ilutp(reorder=True)
+        log = ctx.run_steps_logged(s.n)
+        s0 = ctx.stats()[0]
+        e, (terms,) = ctx.kinetic_energy(terms=True)
+        s1 = ctx.stats()[0]
+        ctx.close()
+        out[tol] = (terms, s1["iters"] - s0["iters"])
+    pos = positions_after(inst.walkers[0].pos0, _records(log[0]))
+    ref = kinetic_terms(pos, s)
+    res_tol = 10.0 * 1e-6 if not inst.params.mixed else 2.0 * 1e-6
+    bound = _term_bounds(pos, s, np.arange(s.n), res_tol) + 1e-13 * np.abs(ref)
+    err = np.abs(out[1e-6][0] - ref)
+    _say(f"  iterations {out[0.0][1]} at the ratio tolerance, {out[1e-6][1]} at 1e-6; "
+         f"max |dt| {err.max():.3e}, max |dt|/bound {np.max(err / bound):.3e}")
+    assert np.all(err <= bound)
+    assert out[1e-6][1] < out[0.0][1]
+
+
 def test_kinetic_energy_rejects_pending_move(vm):
     _say("case: kinetic energy with a pending move")
     inst = wl.plain_n128()
