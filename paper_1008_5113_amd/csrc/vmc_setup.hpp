@@ -268,7 +268,7 @@ __device__ inline int ilu_compact(IluWave& R, int ncand) {
 __device__ inline int ilu_add_cands(const Walker& W, IluWave& R, int ncand, bool add, int p, int c, int cap) {
   const int lane = lane_id();
   const unsigned long long mask = __ballot(add);
-  if (ncand + __popcll(mask) > cap) ncand = ilu_compact(R, ncand);
+  if (ncand + (int)__popcll(mask) > cap) ncand = ilu_compact(R, ncand);
   const int before = __popcll(mask & ((1ull << lane) - 1ull));
   if (add && ncand + before < cap) {
     const int s = ncand + before;

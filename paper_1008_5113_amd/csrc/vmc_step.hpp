@@ -29,12 +29,7 @@ VMC_PHASE int wg_prepare(const Walker& W, Smem& S, int p, const double* rnew) {
     const int lane = lane_id();
     int st = WST_OK;
     const int cnt = wave_row(W, rnew[0], rnew[1], rnew[2], W.cpos, nc, nv, nullptr, W.W);
-    int ul = 0;
-    if (cnt > W.W) {
-      st = WST_CAPACITY;
-    } else {
-      S.ic[10] = 0;
-    }
+    if (cnt > W.W) st = WST_CAPACITY;
     if (lane == 0) {
       S.ic[4] = i;
       S.ic[5] = cnt;
