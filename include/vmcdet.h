@@ -25,6 +25,8 @@
  *   stream).  Calls that write host outputs synchronise that stream before
  *   returning; vmc_run_steps with a device log pointer is asynchronous.
  * - A context is not thread-safe; one context per stream.
+ * - Walker lists (int32 indices into the context's walkers) may not repeat a
+ *   walker: VMC_EINVAL.  NULL means every walker (count ignored).
  * - Walker w's state: particle positions, the Slater matrix stored by row
  *   positions (a permutation of particles) and column positions (a
  *   permutation of orbitals), the current ILUTP factors and the list of

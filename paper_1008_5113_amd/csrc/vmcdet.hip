@@ -510,8 +510,12 @@ vmc_status launch_setup(Ctx* c, const int* dlist, int count, int mode) {
 vmc_status stage_list(Ctx* c, const int32_t* walkers, int32_t count, int** dlist) {
   if (count < 0 || count > c->nw) { c->err = "bad walker count"; return VMC_EINVAL; }
   if (walkers == nullptr) { *dlist = c->d_all; return VMC_OK; }
-  for (int k = 0; k < count; ++k)
+  std::vector<char> seen(c->nw, 0);
+  for (int k = 0; k < count; ++k) {
     if (walkers[k] < 0 || walkers[k] >= c->nw) { c->err = "walker index out of range"; return VMC_EINVAL; }
+    // one workgroup per listed walker: a walker listed twice would be worked on twice at once
+    if (seen[walkers[k]]++) { c->err = "walker " + std::to_string(walkers[k]) + " listed twice"; return VMC_EINVAL; }
+  }
   HIPCHK(c, hipMemcpyAsync(c->d_list, walkers, sizeof(int) * count, hipMemcpyHostToDevice, c->stream));
   *dlist = c->d_list;
   return VMC_OK;

@@ -1,0 +1,81 @@
+"""Argument and state errors of the C-ABI, and its degenerate calls (empty
+walker lists, zero steps): each returns its documented status and leaves the
+context usable."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def vm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1008_5113_amd as vm
+    vm.lib()  # fails loudly when the library is missing
+    return vm
+
+
+def _status(vm, fn):
+    with pytest.raises(vm.VmcError) as ei:
+        fn()
+    return ei.value.status
+
+
+def test_create_rejects_bad_arguments(vm):
+    _say("case: create with bad arguments")
+    inst = wl.plain_n128()
+    for kw in ({"m_max": 0}, {"gmres_maxit": 0}, {"gmres_maxit": 1000}, {"precision": 7},
+               {"ilu_work_cap": 100000}, {"ilu_drop_norm": 3}):
+        assert _status(vm, lambda: vm.Context.from_instance(inst, **kw)) == vm.vmcdet.VMC_EINVAL, kw
+    s = inst.systems[0]
+    p = vm.default_params()
+    bad = wl.System(lattice=s.lattice, a=s.a, sites=s.sites, sigma=s.sigma, kind=s.kind, p_scale=0.0,
+                    p_sigma=0.5, cutoff=0.0)
+    assert _status(vm, lambda: vm.Context([bad], [(0, inst.walkers[0].pos0, 0)], p)) == vm.vmcdet.VMC_EINVAL
+
+
+def test_row_capacity_error(vm):
+    _say("case: Slater rows beyond the row capacity")
+    inst = wl.plain_n128()
+    ctx = vm.Context.from_instance(inst, row_cap=16)
+    assert _status(vm, ctx.build_slater) == vm.vmcdet.VMC_ECAPACITY
+    ctx.close()
+
+
+def test_walker_lists_and_states(vm):
+    _say("case: walker lists, pending state, zero steps")
+    inst = wl.small_instance(lattice=(4, 4, 4), n_walkers=3)
+    ctx = vm.Context.from_instance(inst)
+    ctx.ilutp(reorder=True)
+    # empty lists and zero steps do nothing
+    r, _ = ctx.det_ratio(walkers=np.zeros(0, dtype=np.int32))
+    assert r.size == 0
+    ctx.run_steps(0)
+    # out of range and repeated walkers
+    assert _status(vm, lambda: ctx.det_ratio(walkers=[3])) == vm.vmcdet.VMC_EINVAL
+    assert _status(vm, lambda: ctx.det_ratio(walkers=[1, 1])) == vm.vmcdet.VMC_EINVAL
+    # accept without a pending ratio
+    assert _status(vm, lambda: ctx.accept(walkers=[0])) == vm.VMC_ESTATE
+    # explicit move outside the box
+    assert _status(vm, lambda: ctx.det_ratio(walkers=[0], particles=[0],
+                                             new_pos=[[-1.0, 0.0, 0.0]])) == vm.vmcdet.VMC_EINVAL
+    # the context still works
+    r, info = ctx.det_ratio(walkers=[2, 0])
+    assert np.all(np.isfinite(r)) and np.all(info["flags"] & vm.FLAG_CONVERGED)
+    acc = ctx.accept(walkers=[2, 0])
+    assert acc.shape == (2,)
+    ctx.run_steps(10)
+    ctx.sync()
+    assert all(st["status"] == 0 for st in ctx.stats())
+    ctx.close()
