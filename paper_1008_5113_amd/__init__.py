@@ -11,4 +11,6 @@ from .vmcdet import (Context, STEP_RECORD_DTYPE, VmcError, default_params, param
                      VMC_ESTATE)
 
 __all__ = ["Context", "STEP_RECORD_DTYPE", "VmcError", "default_params", "params_from_workload",
-           "PREC_FP64", "PREC_MIXED", "LIB_PATH", "load_library", "lib"]
+           "PREC_FP64", "PREC_MIXED", "FLAG_ACCEPTED", "FLAG_REORDERED", "FLAG_REFACTORED",
+           "FLAG_CONVERGED", "FLAG_SINGULAR", "FLAG_CAPACITY", "VMC_ESTATE", "LIB_PATH",
+           "load_library", "lib"]

@@ -7,7 +7,7 @@ import pytest
 import workloads as wl
 from oracle.chain import free_run
 from oracle.geometry import orbital_values, slater_dense
-from oracle.ratio import StandardAlgorithm, det_leibniz, ratio_leibniz, ratio_lu
+from oracle.ratio import det_leibniz, ratio_leibniz, ratio_lu
 from oracle.reorder import geometric_reorder, inverse_perm
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
