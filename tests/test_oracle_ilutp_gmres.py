@@ -1,4 +1,6 @@
 """Pins for the oracle's ILUTP, GMRES, effective stability and product-form update."""
+import os
+
 import numpy as np
 import pytest
 import scipy.linalg as sla
@@ -172,3 +174,21 @@ def test_update_identity_exact_z():
     diff = A1 @ M2.apply(v) - A @ M.apply(v)
     pred = r2 * (u @ M.apply(v)) / ratio2
     assert np.linalg.norm(diff - pred) <= 1e-10 * np.linalg.norm(pred)
+
+
+def test_stability_study_runs_and_orders_measures():
+    """The N1/N2/N study script on a small b.c.c. system: it runs, and with the
+    pivoting the paper workload uses the accuracy is good and GMRES converges."""
+    import subprocess
+    import sys as _sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([_sys.executable, os.path.join(root, "tests", "study_preconditioner_stability.py"),
+                          "--K", "4", "--configs", "3"], capture_output=True, text=True, check=True).stdout
+    lines = [l for l in out.splitlines() if "N1/|A|" in l]
+    assert len(lines) == 3
+    for l in lines:
+        f = l.split()
+        its_max = int(f[2].split("-")[1])
+        n1 = float(f[f.index("N1/|A|") + 1])
+        assert its_max < 40 and n1 < 0.1
+    assert "rank correlation" in out
