@@ -288,9 +288,14 @@ vmc_status vmc_run_steps_energy(void* ctx, int32_t steps, vmc_step_record* dev_l
    vmc_sm_run_steps then takes `steps` steps of every walker by the standard
    algorithm: the same proposals, draws and decision rule as vmc_run_steps
    (ratio = a'^T A^{-1} e_p), records in dev_log as vmc_run_steps writes them
-   (iters 0, N 0).  It moves the particles but leaves the sparse state (A, the
-   factors, the update list) behind: call vmc_build_slater and vmc_ilutp before
-   sparse steps again.  Asynchronous.
+   (iters 0, N 0).  VMC_ESTATE before vmc_sm_prepare, or when any other call
+   that may move a walker or rebuild its rows (vmc_build_slater, vmc_ilutp,
+   vmc_det_ratio, vmc_accept, the vmc_run_* calls, vmc_phase_bench) came after
+   the last vmc_sm_prepare.  It moves the particles but leaves the sparse state
+   (A, the factors, the update list) behind: until vmc_build_slater and then
+   vmc_ilutp (or vmc_ilutp with reorder) have rebuilt a walker, the sparse-path
+   calls on it (vmc_det_ratio, vmc_accept, vmc_kinetic_energy, the vmc_run_*
+   calls, vmc_sm_prepare, vmc_phase_bench) return VMC_ESTATE.  Asynchronous.
    vmc_sm_get_inverse copies walker w's inverse to host_out (n*n doubles,
    host_out[p*n + j] = (A^{-1})_{jp}, particle p, site j).  Synchronous. */
 vmc_status vmc_sm_prepare(void* ctx, double tol);

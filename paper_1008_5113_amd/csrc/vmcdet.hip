@@ -478,6 +478,13 @@ struct Ctx {
   double** d_smB = nullptr;
   int* d_nonconv = nullptr;
   int max_cap = 0;
+  // the stored inverses belong to the walkers' current matrices: set by
+  // vmc_sm_prepare, kept by vmc_sm_run_steps, cleared by every other call that
+  // may move a walker, rebuild its rows or reorder them
+  bool sm_current = false;
+  // per walker: positions moved by vmc_sm_run_steps since its rows (A) or its
+  // factors were last rebuilt, so the sparse path would use stale matrices
+  std::vector<char> rows_stale, fac_stale;
   std::string err;
 };
 
@@ -518,6 +525,19 @@ vmc_status stage_list(Ctx* c, const int32_t* walkers, int32_t count, int** dlist
   }
   HIPCHK(c, hipMemcpyAsync(c->d_list, walkers, sizeof(int) * count, hipMemcpyHostToDevice, c->stream));
   *dlist = c->d_list;
+  return VMC_OK;
+}
+
+vmc_status check_sparse(Ctx* c, const int32_t* walkers, int32_t count) {
+  for (int k = 0; k < count; ++k) {
+    const int w = walkers ? walkers[k] : k;
+    if (c->rows_stale[w] || c->fac_stale[w]) {
+      c->err = "walker " + std::to_string(w) +
+               ": moved by vmc_sm_run_steps; rebuild its rows and factors (vmc_build_slater, then vmc_ilutp, or "
+               "vmc_ilutp with reorder) first";
+      return VMC_ESTATE;
+    }
+  }
   return VMC_OK;
 }
 
@@ -620,12 +640,15 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
   auto fail = [&](vmc_status s, const std::string& msg) {
     g_create_error = msg;
     for (void* a : c->arenas) (void)hipFree(a);
-    if (c->dW) (void)hipFree(c->dW);
-    if (c->dS) (void)hipFree(c->dS);
+    for (void* q : {(void*)c->dW, (void*)c->dS, (void*)c->d_list, (void*)c->d_all, (void*)c->d_part, (void*)c->d_pos,
+                    (void*)c->d_rec, (void*)c->d_dec, (void*)c->d_acc, (void*)c->d_err, (void*)c->d_order})
+      if (q) (void)hipFree(q);
     delete c;
     return s;
   };
   c->hw.resize(n_walkers);
+  c->rows_stale.assign(n_walkers, 0);
+  c->fac_stale.assign(n_walkers, 0);
   for (int w = 0; w < n_walkers; ++w) {
     const vmc_walker_init& in = wi[w];
     const int n = in.n;
@@ -772,7 +795,8 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
   if (hipMalloc(&c->dW, sizeof(Walker) * n_walkers) != hipSuccess ||
       hipMalloc(&c->dS, sizeof(WalkerState) * n_walkers) != hipSuccess)
     return fail(VMC_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(hipGetLastError()));
-  (void)hipMemcpy(c->dW, c->hw.data(), sizeof(Walker) * n_walkers, hipMemcpyHostToDevice);
+  if (hipMemcpy(c->dW, c->hw.data(), sizeof(Walker) * n_walkers, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(VMC_EHIP, "initial copy failed");
   {
     std::vector<WalkerState> hs(n_walkers);
     std::memset(hs.data(), 0, sizeof(WalkerState) * n_walkers);
@@ -793,7 +817,8 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
   ok &= hipMalloc(&c->d_err, sizeof(int) * n_walkers) == hipSuccess;
   ok &= hipMalloc(&c->d_order, sizeof(int) * n_walkers) == hipSuccess;
   if (!ok) return fail(VMC_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(hipGetLastError()));
-  (void)hipMemcpy(c->d_all, all.data(), sizeof(int) * n_walkers, hipMemcpyHostToDevice);
+  if (hipMemcpy(c->d_all, all.data(), sizeof(int) * n_walkers, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(VMC_EHIP, "initial copy failed");
 
   int dev = 0, maxlds = 0;
   (void)hipGetDevice(&dev);
@@ -833,6 +858,7 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
 vmc_status vmc_build_slater(void* ctx, const int32_t* walkers, int32_t count) {
   Ctx* c = (Ctx*)ctx;
   if (!c) return VMC_EINVAL;
+  c->sm_current = false;
   if (!walkers) count = c->nw;
   int* dl = nullptr;
   vmc_status s = stage_list(c, walkers, count, &dl);
@@ -841,12 +867,16 @@ vmc_status vmc_build_slater(void* ctx, const int32_t* walkers, int32_t count) {
   s = c->dp.precision == VMC_PREC_FP64 ? launch_setup<VMC_PREC_FP64>(c, dl, count, MODE_BUILD)
                                        : launch_setup<VMC_PREC_MIXED>(c, dl, count, MODE_BUILD);
   if (s) return s;
-  return walker_errors(c);
+  s = walker_errors(c);
+  if (s) return s;
+  for (int k = 0; k < count; ++k) c->rows_stale[walkers ? walkers[k] : k] = 0;
+  return VMC_OK;
 }
 
 vmc_status vmc_ilutp(void* ctx, const int32_t* walkers, int32_t count, int32_t reorder) {
   Ctx* c = (Ctx*)ctx;
   if (!c) return VMC_EINVAL;
+  c->sm_current = false;
   if (!walkers) count = c->nw;
   int* dl = nullptr;
   vmc_status s = stage_list(c, walkers, count, &dl);
@@ -856,19 +886,29 @@ vmc_status vmc_ilutp(void* ctx, const int32_t* walkers, int32_t count, int32_t r
   s = c->dp.precision == VMC_PREC_FP64 ? launch_setup<VMC_PREC_FP64>(c, dl, count, mode)
                                        : launch_setup<VMC_PREC_MIXED>(c, dl, count, mode);
   if (s) return s;
-  return walker_errors(c);
+  s = walker_errors(c);
+  if (s) return s;
+  for (int k = 0; k < count; ++k) {
+    const int w = walkers ? walkers[k] : k;
+    if (reorder) c->rows_stale[w] = 0;  // the reorder rebuilds every row in the new order
+    if (!c->rows_stale[w]) c->fac_stale[w] = 0;
+  }
+  return VMC_OK;
 }
 
 vmc_status vmc_det_ratio(void* ctx, const int32_t* walkers, int32_t count, const int32_t* particle,
                          const double* new_pos, double* ratio_out, vmc_step_record* info_out) {
   Ctx* c = (Ctx*)ctx;
   if (!c || !ratio_out || count < 0) return VMC_EINVAL;
+  c->sm_current = false;
   if (!walkers) count = c->nw;
   if ((particle == nullptr) != (new_pos == nullptr)) { c->err = "particle and new_pos go together"; return VMC_EINVAL; }
   int* dl = nullptr;
   vmc_status s = stage_list(c, walkers, count, &dl);
   if (s) return s;
   if (count == 0) return VMC_OK;
+  s = check_sparse(c, walkers, count);
+  if (s) return s;
   if (particle) {
     for (int k = 0; k < count; ++k) {
       const int w = walkers ? walkers[k] : k;
@@ -907,11 +947,14 @@ vmc_status vmc_accept(void* ctx, const int32_t* walkers, int32_t count, const ui
                       uint8_t* accepted_out) {
   Ctx* c = (Ctx*)ctx;
   if (!c || count < 0) return VMC_EINVAL;
+  c->sm_current = false;
   if (!walkers) count = c->nw;
   int* dl = nullptr;
   vmc_status s = stage_list(c, walkers, count, &dl);
   if (s) return s;
   if (count == 0) return VMC_OK;
+  s = check_sparse(c, walkers, count);
+  if (s) return s;
   if (accept) HIPCHK(c, hipMemcpyAsync(c->d_dec, accept, count, hipMemcpyHostToDevice, c->stream));
   if (c->dp.precision == VMC_PREC_FP64)
     hipLaunchKernelGGL(k_accept<VMC_PREC_FP64>, dim3(count), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, dl,
@@ -932,6 +975,7 @@ vmc_status vmc_accept(void* ctx, const int32_t* walkers, int32_t count, const ui
 }
 
 static void launch_run(Ctx* c, int steps, vmc_step_record* dev_log, long long cap) {
+  c->sm_current = false;
   const int* order = c->use_order ? c->d_order : nullptr;
   if (c->dp.precision == VMC_PREC_FP64)
     hipLaunchKernelGGL(k_run<VMC_PREC_FP64>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, steps,
@@ -945,6 +989,7 @@ vmc_status vmc_run_steps(void* ctx, int32_t steps, vmc_step_record* dev_log, int
   Ctx* c = (Ctx*)ctx;
   if (!c || steps < 0) return VMC_EINVAL;
   if (steps == 0) return VMC_OK;
+  if (vmc_status s = check_sparse(c, nullptr, c->nw)) return s;
   launch_run(c, steps, dev_log, (long long)(dev_log ? log_cap : 0));
   HIPCHK(c, hipGetLastError());
   return VMC_OK;
@@ -954,6 +999,8 @@ vmc_status vmc_run_steps_graph(void* ctx, int32_t steps, vmc_step_record* dev_lo
   Ctx* c = (Ctx*)ctx;
   if (!c || steps < 0) return VMC_EINVAL;
   if (steps == 0) return VMC_OK;
+  if (vmc_status s = check_sparse(c, nullptr, c->nw)) return s;
+  c->sm_current = false;
   if (!c->stream) {
     c->err = "vmc_run_steps_graph needs a context created on a non-default stream";
     return VMC_EINVAL;
@@ -1021,6 +1068,7 @@ vmc_status vmc_run_steps_energy(void* ctx, int32_t steps, vmc_step_record* dev_l
   if (!c || steps < 0 || energy_cap < 0 || (energy_cap > 0 && !dev_energy)) return VMC_EINVAL;
   if (steps == 0) return VMC_OK;
   if (!c->all_same_n) { c->err = "vmc_run_steps_energy needs walkers of equal n"; return VMC_EINVAL; }
+  if (vmc_status s = check_sparse(c, nullptr, c->nw)) return s;
   std::vector<WalkerState> hs(c->nw);
   HIPCHK(c, hipMemcpyAsync(hs.data(), c->dS, sizeof(WalkerState) * c->nw, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1074,6 +1122,8 @@ vmc_status vmc_kinetic_energy(void* ctx, const int32_t* walkers, int32_t count, 
   vmc_status s = stage_list(c, walkers, count, &dl);
   if (s) return s;
   if (count == 0) return VMC_OK;
+  s = check_sparse(c, walkers, count);
+  if (s) return s;
   std::vector<long long> toff(count);
   long long tot = 0;
   for (int k = 0; k < count; ++k) {
@@ -1116,6 +1166,7 @@ vmc_status vmc_kinetic_energy(void* ctx, const int32_t* walkers, int32_t count, 
 vmc_status vmc_sm_prepare(void* ctx, double tol) {
   Ctx* c = (Ctx*)ctx;
   if (!c || !(tol > 0.0)) return VMC_EINVAL;
+  if (vmc_status s = check_sparse(c, nullptr, c->nw)) return s;
   if (!c->d_smB) {
     std::vector<double*> ptrs(c->nw);
     for (int w = 0; w < c->nw; ++w) {
@@ -1132,13 +1183,21 @@ vmc_status vmc_sm_prepare(void* ctx, double tol) {
       c->sm_bufs.push_back(b);
       ptrs[w] = (double*)b;
     }
-    if (hipMalloc(&c->d_smB, sizeof(double*) * c->nw) != hipSuccess ||
-        hipMalloc(&c->d_nonconv, sizeof(int) * c->nw) != hipSuccess) {
+    // the table and the flags are set together, so a failed call leaves neither
+    void* tab = nullptr;
+    void* flags = nullptr;
+    if (hipMalloc(&tab, sizeof(double*) * c->nw) != hipSuccess || hipMalloc(&flags, sizeof(int) * c->nw) != hipSuccess) {
+      if (tab) (void)hipFree(tab);
+      for (void* q : c->sm_bufs) (void)hipFree(q);
+      c->sm_bufs.clear();
       c->err = "device allocation failed";
       return VMC_ENOMEM;
     }
+    c->d_smB = (double**)tab;
+    c->d_nonconv = (int*)flags;
     HIPCHK(c, hipMemcpyAsync(c->d_smB, ptrs.data(), sizeof(double*) * c->nw, hipMemcpyHostToDevice, c->stream));
   }
+  c->sm_current = false;
   if (c->dp.precision == VMC_PREC_FP64)
     hipLaunchKernelGGL(k_inverse_cols<VMC_PREC_FP64>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp,
                        (double* const*)c->d_smB, 0, c->maxn, tol, c->d_nonconv);
@@ -1156,19 +1215,27 @@ vmc_status vmc_sm_prepare(void* ctx, double tol) {
       return VMC_ENOCONV;
     }
   }
-  return walker_errors(c);
+  const vmc_status st = walker_errors(c);
+  c->sm_current = (st == VMC_OK);
+  return st;
 }
 
 vmc_status vmc_sm_run_steps(void* ctx, int32_t steps, vmc_step_record* dev_log, int64_t log_cap) {
   Ctx* c = (Ctx*)ctx;
   if (!c || steps < 0) return VMC_EINVAL;
   if (!c->d_smB) { c->err = "vmc_sm_run_steps before vmc_sm_prepare"; return VMC_ESTATE; }
+  if (!c->sm_current) {
+    c->err = "the stored inverses are stale: the walkers have changed since vmc_sm_prepare";
+    return VMC_ESTATE;
+  }
   if (steps == 0) return VMC_OK;
   const size_t lds = sm_lds(c->maxn, c->max_cap).total;
   (void)hipFuncSetAttribute((const void*)k_sm_run, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k_sm_run, dim3(c->nw), dim3(NT), lds, c->stream, c->dW, c->dS, c->dp, (double* const*)c->d_smB,
                      steps, dev_log, (long long)(dev_log ? log_cap : 0));
   HIPCHK(c, hipGetLastError());
+  c->rows_stale.assign(c->nw, 1);
+  c->fac_stale.assign(c->nw, 1);
   return VMC_OK;
 }
 
@@ -1298,6 +1365,8 @@ vmc_status vmc_autotune(void* ctx, const char* cache_path, int32_t trial_steps, 
 vmc_status vmc_phase_bench(void* ctx, int32_t phase, int32_t reps) {
   Ctx* c = (Ctx*)ctx;
   if (!c || phase < 0 || phase > 5 || reps < 0) return VMC_EINVAL;
+  if (vmc_status s = check_sparse(c, nullptr, c->nw)) return s;
+  c->sm_current = false;
   if (c->dp.precision == VMC_PREC_FP64) {
     (void)hipFuncSetAttribute((const void*)k_phase<VMC_PREC_FP64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds);
     hipLaunchKernelGGL(k_phase<VMC_PREC_FP64>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, phase, reps);

@@ -112,3 +112,50 @@ def test_standard_requires_prepare(vm):
         ctx.sm_run_steps(1)
     assert ei.value.status == vm.VMC_ESTATE
     ctx.close()
+
+
+def test_standard_and_sparse_state_guards(vm):
+    """A stored inverse is refused once a sparse-path call has run after it; the
+    sparse path is refused on walkers the standard algorithm moved until their
+    rows and factors are rebuilt, and after the rebuild its ratios match the
+    oracle from the moved positions."""
+    _say("case: standard/sparse state guards plain_n128")
+    inst = wl.plain_n128()
+    s = inst.systems[0]
+    ctx = vm.Context.from_instance(inst)
+    ctx.ilutp(reorder=True)
+    ctx.sm_prepare(TOL)
+    ctx.run_steps(4)
+    ctx.sync()
+    with pytest.raises(vm.VmcError) as ei:
+        ctx.sm_run_steps(1)
+    assert ei.value.status == vm.VMC_ESTATE
+    ctx.sm_prepare(TOL)
+    ctx.sm_run_steps(6)
+    ctx.sync()
+    for call in (lambda: ctx.run_steps(1), lambda: ctx.sm_prepare(TOL), lambda: ctx.kinetic_energy(p_end=1),
+                 lambda: ctx.det_ratio()):
+        with pytest.raises(vm.VmcError) as ei:
+            call()
+        assert ei.value.status == vm.VMC_ESTATE
+    ctx.build_slater()
+    with pytest.raises(vm.VmcError) as ei:  # rows rebuilt, factors still of the old rows
+        ctx.run_steps(1)
+    assert ei.value.status == vm.VMC_ESTATE
+    ctx.ilutp(reorder=False)
+    pos_mid = ctx.state(0)["pos"]
+    log = ctx.run_steps_logged(s.n)
+    stats = ctx.stats()[0]
+    assert stats["status"] == 0
+    rep = replay(s, pos_mid, inst.walkers[0].seed, inst.params.step, _records(log[0]), dec_tol=DEC_TOL)
+    _say(f"  sparse steps after standard steps: max dlog {rep.max_dlog:.3e}, decisions off {rep.decision_mismatch}")
+    assert rep.pos_mismatch == 0 and rep.sign_mismatch == 0
+    assert rep.decision_mismatch_outside_tol == 0
+    assert rep.max_dlog < DLOG_TOL
+    # a reorder rebuilds the rows itself
+    ctx.sm_prepare(TOL)
+    ctx.sm_run_steps(3)
+    ctx.ilutp(reorder=True)
+    ctx.run_steps(3)
+    ctx.sync()
+    ctx.close()
