@@ -103,6 +103,13 @@ class ReplayReport:
     decision_mismatch_outside_tol: int = 0
     oracle_ratios: list = dataclasses.field(default_factory=list)
 
+    def summary(self) -> str:
+        """Max and 99.9th percentile of |dln|ratio|| over the checked steps,
+        and the decision mismatches (all, and those outside the tolerance)."""
+        p999 = float(np.percentile(self.dlogs, 99.9)) if self.dlogs else 0.0
+        return (f"{self.steps} steps: max dlog {self.max_dlog:.3e}, p99.9 {p999:.3e}; "
+                f"decisions off {self.decision_mismatch} ({self.decision_mismatch_outside_tol} outside tol)")
+
 
 def replay(system, pos0, seed: int, h: float, log, dec_tol: float = 1e-9,
            mode: str = "lu", check_every: int = 1) -> ReplayReport:

@@ -80,6 +80,6 @@ def test_paper_experiment_n686(vm):
     f = np.abs(np.minimum(q, 1.0) - np.minimum(qa, 1.0))
     _say(f"  walker 0, {len(f)} steps: mean f {f.mean():.3e}; f < 1e-4: {np.mean(f < 1e-4) * 100:.2f}%, "
          f"< 1e-3: {np.mean(f < 1e-3) * 100:.2f}%, < 1e-2: {np.mean(f < 1e-2) * 100:.2f}%; "
-         f"max dlog {rep.max_dlog:.3e}; decisions off {rep.decision_mismatch}")
+         f"{rep.summary()}")
     assert np.all(f < 1e-2)
     assert rep.decision_mismatch_outside_tol == 0

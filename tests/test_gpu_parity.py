@@ -222,7 +222,7 @@ def test_free_run_plain_n128(vm, precision):
     steps = 4 * inst.systems[0].n
     (res,), stats = _free_run_check(vm, inst, steps, precision)
     rep, log = res
-    _say(f"  max dlog {rep.max_dlog:.3e} acc {np.mean(log['flags'] & 1):.3f} "
+    _say(f"  {rep.summary()}; acc {np.mean(log['flags'] & 1):.3f} "
          f"iters {np.mean(log['iters']):.2f} stats {stats[0]}")
     assert rep.pos_mismatch == 0
     assert rep.sign_mismatch == 0
@@ -272,8 +272,7 @@ def _full_config(vm, inst, steps, sample, precision=None):
         s = inst.system_of(w)
         rep = replay(s, inst.walkers[w].pos0, inst.walkers[w].seed, inst.params.step, _records(log[w]),
                      dec_tol=DEC_TOL, mode="sm")
-        _say(f"  walker {w} n={s.n}: max dlog {rep.max_dlog:.3e} "
-             f"decisions off {rep.decision_mismatch} (outside tol {rep.decision_mismatch_outside_tol})")
+        _say(f"  walker {w} n={s.n}: {rep.summary()}")
         assert rep.pos_mismatch == 0 and rep.sign_mismatch == 0
         assert rep.decision_mismatch_outside_tol == 0
         assert rep.max_dlog < DLOG_TOL

@@ -76,8 +76,7 @@ def test_standard_steps_replay(vm):
     assert stats["status"] == 0 and stats["steps"] == 2 * s.n
     recs = _records(log[0])
     rep = replay(s, inst.walkers[0].pos0, inst.walkers[0].seed, inst.params.step, recs, dec_tol=DEC_TOL)
-    _say(f"  max dlog {rep.max_dlog:.3e}, acceptance {np.mean([r.accepted for r in recs]):.3f}, "
-         f"decisions off {rep.decision_mismatch}")
+    _say(f"  {rep.summary()}; acceptance {np.mean([r.accepted for r in recs]):.3f}")
     assert rep.pos_mismatch == 0 and rep.sign_mismatch == 0
     assert rep.decision_mismatch_outside_tol == 0
     assert rep.max_dlog < DLOG_TOL
@@ -99,7 +98,7 @@ def test_standard_full_size_sampled(vm):
     assert all(st["status"] == 0 for st in stats)
     rep = replay(s, inst.walkers[0].pos0, inst.walkers[0].seed, inst.params.step, _records(log[0]),
                  dec_tol=DEC_TOL, mode="sm")
-    _say(f"  walker 0: max dlog {rep.max_dlog:.3e}, decisions off {rep.decision_mismatch}")
+    _say(f"  walker 0: {rep.summary()}")
     assert rep.pos_mismatch == 0 and rep.sign_mismatch == 0
     assert rep.decision_mismatch_outside_tol == 0
     assert rep.max_dlog < DLOG_TOL
@@ -148,7 +147,7 @@ def test_standard_and_sparse_state_guards(vm):
     stats = ctx.stats()[0]
     assert stats["status"] == 0
     rep = replay(s, pos_mid, inst.walkers[0].seed, inst.params.step, _records(log[0]), dec_tol=DEC_TOL)
-    _say(f"  sparse steps after standard steps: max dlog {rep.max_dlog:.3e}, decisions off {rep.decision_mismatch}")
+    _say(f"  sparse steps after standard steps: {rep.summary()}")
     assert rep.pos_mismatch == 0 and rep.sign_mismatch == 0
     assert rep.decision_mismatch_outside_tol == 0
     assert rep.max_dlog < DLOG_TOL
