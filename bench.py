@@ -398,8 +398,8 @@ def main():
     if args.steps % args.chunk or args.warmup % args.chunk:
         ap.error("--steps and --warmup must be multiples of --chunk")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: walkers are independent chains and this build "
-              "measures one GPU's share; use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: walkers are independent chains, so the benchmark "
+              "measures one GPU's share of them; use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     import workloads as wl
