@@ -253,6 +253,11 @@ class Context:
             sites = np.ascontiguousarray(s.sites, dtype=np.float64)
             sigma = np.ascontiguousarray(s.sigma, dtype=np.float64)
             pos = np.ascontiguousarray(pos0, dtype=np.float64)
+            # the library copies n*3, n and n*3 doubles from these arrays
+            n = sites.shape[0] if sites.ndim == 2 else -1
+            if sites.shape != (n, 3) or sigma.shape != (n,) or pos.shape != (n, 3):
+                raise ValueError(f"walker {k}: sites {sites.shape}, sigma {sigma.shape} and positions "
+                                 f"{pos.shape} must be (n, 3), (n,) and (n, 3)")
             self._keep += [sites, sigma, pos]
             w = inits[k]
             w.n = sites.shape[0]
@@ -328,8 +333,11 @@ class Context:
         count = cnt if w is not None else self.n_walkers
         ratio = np.zeros(count, dtype=np.float64)
         info = np.zeros(count, dtype=STEP_RECORD_DTYPE)
-        part = None if particles is None else np.ascontiguousarray(particles, dtype=np.int32)
+        part = None if particles is None else np.ascontiguousarray(particles, dtype=np.int32).reshape(-1)
         pos = None if new_pos is None else np.ascontiguousarray(new_pos, dtype=np.float64).reshape(-1)
+        # the library reads count particles and 3*count coordinates
+        if (part is not None and part.size != count) or (pos is not None and pos.size != 3 * count):
+            raise ValueError(f"{count} walkers need {count} particles and {3 * count} coordinates")
         st = lib().vmc_det_ratio(self.h, _ptr(w), count, _ptr(part), _ptr(pos), _ptr(ratio),
                                  info.ctypes.data_as(ctypes.c_void_p))
         if check:
@@ -339,7 +347,9 @@ class Context:
     def accept(self, walkers=None, decisions=None):
         w, cnt = self._wl(walkers)
         count = cnt if w is not None else self.n_walkers
-        dec = None if decisions is None else np.ascontiguousarray(decisions, dtype=np.uint8)
+        dec = None if decisions is None else np.ascontiguousarray(decisions, dtype=np.uint8).reshape(-1)
+        if dec is not None and dec.size != count:
+            raise ValueError(f"{count} walkers need {count} decisions")
         out = np.zeros(count, dtype=np.uint8)
         self._check(lib().vmc_accept(self.h, _ptr(w), count, _ptr(dec), _ptr(out)))
         return out.astype(bool)

@@ -58,3 +58,24 @@ def test_default_params_without_gpu():
     import paper_1008_5113_amd as vm
     p = vm.default_params()
     assert p.gmres_maxit == 40 and p.droptol == 1e-4 and p.permtol == 0.1 and p.n_thresh == 100.0
+
+
+def test_binding_rejects_mismatched_arrays_before_the_library():
+    """The binding checks the array shapes the library will copy from (n*3
+    sites, n widths, n*3 positions) and raises before any device call."""
+    from paper_1008_5113_amd.vmcdet import LIB_PATH
+    if not os.path.exists(LIB_PATH):
+        pytest.skip("library not built")
+    import numpy as np
+    import paper_1008_5113_amd as vm
+    import workloads as wl
+    inst = wl.small_instance((2, 2, 2))
+    s = inst.systems[0]
+    good = inst.walkers[0].pos0
+    for bad in (good[:-1], good[:, :2], good.reshape(-1)):
+        with pytest.raises(ValueError):
+            vm.Context([s], [(0, bad, 0)], vm.default_params())
+    s2 = wl.make_system((2, 2, 2))
+    s2.sigma = np.full(s2.sigma.shape[0] - 1, 0.35)
+    with pytest.raises(ValueError):
+        vm.Context([s2], [(0, good, 0)], vm.default_params())
