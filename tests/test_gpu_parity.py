@@ -315,6 +315,21 @@ def test_full_size_stress_n8192(vm):
     _full_config(vm, inst, 60, (0,))
 
 
+def test_maximum_n(vm):
+    """The largest n the library admits, 16384 (16x32x32, sc lattice, rc 2.0):
+    in mixed precision one workgroup's LDS holds the staged FP32 vectors, so
+    two walkers run 24 steps in one launch and walker 0 is replayed by the
+    oracle's standard algorithm; in FP64 the staged vector alone needs 128 KiB
+    and create refuses the size with VMC_EINVAL."""
+    _say("case: maximum n = 16384: FP64 refused, mixed 2 walkers x 24 steps")
+    inst = wl.small_instance(lattice=(16, 32, 32), n_walkers=2, mixed=True)
+    assert inst.systems[0].n == 16384
+    with pytest.raises(vm.VmcError) as ei:
+        vm.Context.from_instance(inst, precision=0)
+    assert ei.value.status == vm.vmcdet.VMC_EINVAL and "LDS" in str(ei.value)
+    _full_config(vm, inst, 24, (0,))
+
+
 def test_graph_replays_match_direct_launches(vm):
     """The persistent launch captured in a HIP graph and replayed three times
     (with ordinary host work and synchronisation between replays) gives the
