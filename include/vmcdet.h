@@ -199,7 +199,13 @@ typedef struct vmc_tune_info {
 vmc_status vmc_default_params(vmc_params* p);
 
 /* Create a context for n_walkers walkers; copies all host arrays.  hip_stream
-   is a hipStream_t (NULL for the default stream). */
+   is a hipStream_t (NULL for the default stream).  One workgroup works on one
+   walker with its vectors staged in LDS, so the largest n must fit one
+   workgroup's LDS: on a 160 KiB device n = 16384 fits in mixed precision and
+   FP64 stops near n = 14700 (less with a larger m_max); a larger n returns
+   VMC_EINVAL with the bytes needed in vmc_last_error(NULL).  VMC_ENOMEM when
+   a walker's device arena cannot be allocated.  On any error nothing stays
+   allocated and no context is returned. */
 vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers,
                       const vmc_walker_init* walkers, void* hip_stream);
 
