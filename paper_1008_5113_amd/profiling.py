@@ -1,4 +1,5 @@
-"""Summaries of rocprofv3 output for the fused step kernel.
+"""Summaries of rocprofv3 output for the fused step kernel and the per-phase
+micro-benchmarks.
 
 ``python -m paper_1008_5113_amd.profiling summarize --trace DIR --fetch DIR --write DIR
 --copy-fetch DIR --copy-write DIR --out-json FILE`` reads the CSV files that
@@ -9,6 +10,11 @@ the per-launch figures of the step kernel (every launch covers the same number
 of steps) to a JSON file, with the launch configuration it was taken at.  The JSON
 records a hash of the kernel sources; bench.py reports the traffic only while
 the sources still hash the same.
+
+``python -m paper_1008_5113_amd.profiling phases --trace DIR --fetch DIR --write DIR
+--copy-fetch DIR --copy-write DIR --bench-log FILE --out-md FILE`` does the same
+for ``bench.py --phases`` runs: per phase, the traced duration, algorithmic and
+HBM bytes, and both rates against the 8 TB/s peak.
 """
 from __future__ import annotations
 
@@ -148,9 +154,69 @@ def to_markdown(d, commands, bench_line=None):
     return "\n".join(L) + "\n"
 
 
+PHASE_ORDER = ("spmv", "lsolve", "usolve", "updates", "resid64")
+
+
+def summarize_phases(trace, fetch, write, copy_fetch, copy_write, bench_log, hbm_peak_gbs=8000.0):
+    """Per-phase figures of ``bench.py --phases`` runs: the k_phase launches in
+    the order bench.py issues them (per path, the phases of PHASE_ORDER that it
+    runs), each with its traced duration, its algorithmic bytes (from the bench
+    line: rate times event-timed duration) and its HBM bytes (FETCH_SIZE and
+    WRITE_SIZE scaled by the 1 GiB copy)."""
+    cf = _largest_dispatch(_rows(copy_fetch, "counter_collection.csv"), "copyBuffer")[1]
+    cw = _largest_dispatch(_rows(copy_write, "counter_collection.csv"), "copyBuffer")[1]
+    fetch_scale = COPY_BYTES / (float(cf["Counter_Value"]) * 1024.0)
+    write_scale = COPY_BYTES / (float(cw["Counter_Value"]) * 1024.0)
+    line = None
+    for ln in open(bench_log):
+        if ln.startswith("{"):
+            line = json.loads(ln)
+    labels = []
+    for path, res in line["phases"].items():
+        labels += [(path, ph, res[ph]) for ph in PHASE_ORDER if ph in res]
+    tr = _dispatches(_rows(trace, "kernel_trace.csv"), "k_phase")
+    fr = _dispatches(_rows(fetch, "counter_collection.csv"), "k_phase")
+    wr = _dispatches(_rows(write, "counter_collection.csv"), "k_phase")
+    if not (len(tr) == len(fr) == len(wr) == len(labels)):
+        raise ValueError(f"{len(labels)} phases in the bench line, dispatches: trace {len(tr)}, "
+                         f"fetch {len(fr)}, write {len(wr)}")
+    out = {"fetch_scale": fetch_scale, "write_scale": write_scale, "workload": line.get("workload"),
+           "walkers": line.get("walkers"), "phases": []}
+    for (path, ph, b), t, f, w in zip(labels, tr, fr, wr):
+        ns = int(t["End_Timestamp"]) - int(t["Start_Timestamp"])
+        alg = b["alg_gbs"] * b["ms"] * 1e6
+        hbm = (float(f["Counter_Value"]) * fetch_scale + float(w["Counter_Value"]) * write_scale) * 1024.0
+        out["phases"].append({
+            "path": path, "phase": ph, "trace_ms": ns / 1e6, "event_ms": b["ms"], "us_per_rep": b["us_per_rep"],
+            "alg_bytes": alg, "hbm_bytes": hbm, "alg_gbs": alg / ns, "hbm_gbs": hbm / ns,
+            "alg_frac": alg / ns / hbm_peak_gbs, "hbm_frac": hbm / ns / hbm_peak_gbs})
+    return out
+
+
+def phases_markdown(d, commands):
+    L = [f"# k_phase — per-phase HBM rates, {d['workload']} ({d['walkers']} walkers)", ""]
+    L.append("Every walker's workgroup repeats one phase of the solve at the walker's real shape "
+             "(one launch per phase and path). Algorithmic bytes are the method's own (the "
+             "bench line's rate times its event-timed duration); HBM bytes are FETCH_SIZE and "
+             f"WRITE_SIZE scaled by a 1 GiB device copy (x{d['fetch_scale']:.4f} and "
+             f"x{d['write_scale']:.4f}). Both rates use the traced launch duration; peak 8 TB/s.")
+    L += ["", "## Commands", "", "```"] + commands + ["```", ""]
+    L += ["| path | phase | traced ms | µs per repeat | algorithmic GB/s (of peak) | HBM GB/s (of peak) | "
+          "HBM / algorithmic |", "|---|---|---|---|---|---|---|"]
+    for p in d["phases"]:
+        L.append(f"| {p['path']} | {p['phase']} | {p['trace_ms']:.3f} | {p['us_per_rep']:.1f} | "
+                 f"{p['alg_gbs']:.0f} ({p['alg_frac'] * 100:.0f}%) | {p['hbm_gbs']:.0f} ({p['hbm_frac'] * 100:.0f}%) | "
+                 f"{p['hbm_bytes'] / p['alg_bytes']:.2f} |")
+    return "\n".join(L) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     sp = ap.add_subparsers(dest="cmd")
+    q = sp.add_parser("phases")
+    for k in ("trace", "fetch", "write", "copy_fetch", "copy_write", "bench_log", "out_md"):
+        q.add_argument("--" + k.replace("_", "-"), required=True)
+    q.add_argument("--commands", default=None, help="text file holding the profiling commands")
     s = sp.add_parser("summarize")
     for k in ("trace", "fetch", "write", "copy_fetch", "copy_write"):
         s.add_argument("--" + k.replace("_", "-"), required=True)
@@ -164,8 +230,15 @@ def main():
     s.add_argument("--commands", default=None, help="text file holding the profiling commands")
     s.add_argument("--bench-log", default=None, help="bench.py output of the same configuration")
     args = ap.parse_args()
+    if args.cmd == "phases":
+        d = summarize_phases(args.trace, args.fetch, args.write, args.copy_fetch, args.copy_write, args.bench_log)
+        cmds = open(args.commands).read().splitlines() if args.commands else []
+        with open(args.out_md, "w") as f:
+            f.write(phases_markdown(d, cmds))
+        print(json.dumps(d, indent=1))
+        return
     if args.cmd != "summarize":
-        ap.error("summarize is the only command")
+        ap.error("the commands are summarize and phases")
     launch = {"chunk": args.chunk, "walkers": args.walkers, "m_max": args.m_max, "autotune": args.autotune}
     out = summarize(args.trace, args.fetch, args.write, args.copy_fetch, args.copy_write, args.prec, launch)
     with open(args.out_json, "w") as f:
