@@ -189,6 +189,29 @@ def cpu_baseline(workload, procs, steps):
                        f"inverse set-up untimed; wall {wall:.1f}s")
 
 
+def copy_rate_gbs(nbytes=1 << 30, reps=5):
+    """Bytes read plus written per second by a plain device-to-device copy of
+    nbytes (the best of `reps` event-timed copies): what a streaming kernel
+    reaches on this GPU, beside the published 8 TB/s."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        dst.copy_(src)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (best / 1e3) / 1e9
+
+
 def phase_bench(inst, precision, walkers, stream_ptr, reps, warm_steps, **kw):
     """Per-phase micro-benchmarks at the workload's real shapes (one launch per
     phase, every walker's workgroup repeating the phase `reps` times)."""
@@ -465,6 +488,11 @@ def main():
                                  f"{args.chunk} steps x {nw} walkers per launch",
                        "launch_ms_avg": head["launch_ms_avg"],
                        "alg_bytes_per_launch": head["alg_bytes_per_launch"]}
+    rf = out["roofline"]
+    if rf["traffic"]:
+        rf["traffic_gbs"] = rf["traffic"] / (head["launch_ms_avg"] / 1e3) / 1e9
+    rf["copy_gbs"] = copy_rate_gbs()
+    log(f"plain 1 GiB device copy: {rf['copy_gbs']:.0f} GB/s (bytes read + written)")
     if not args.no_cpu_baseline:
         log(f"cpu baseline: {args.cpu_procs} processes x {args.cpu_steps} oracle steps")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_procs, args.cpu_steps)
