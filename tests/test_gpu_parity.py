@@ -217,9 +217,11 @@ def _free_run_check(vm, inst, steps, precision, walkers=(0,), **kw):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_free_run_plain_n128(vm, precision):
-    _say(f"case: free run plain_n128 precision={precision}")
+    """The 4x4x8 workload's whole run: 20 sweeps of walker 0, every step
+    replayed by dense LU."""
+    _say(f"case: free run plain_n128, 20 sweeps, precision={precision}")
     inst = wl.plain_n128()
-    steps = 4 * inst.systems[0].n
+    steps = 20 * inst.systems[0].n
     (res,), stats = _free_run_check(vm, inst, steps, precision)
     rep, log = res
     _say(f"  {rep.summary()}; acc {np.mean(log['flags'] & 1):.3f} "
