@@ -31,6 +31,9 @@ from .rng import step_draws
 
 @dataclasses.dataclass
 class StepRecord:
+    """One Metropolis step (Section 2.2): the walker's step counter g, the
+    moved particle, its trial position, the ratio, the acceptance draw and the
+    decision."""
     g: int
     particle: int
     new_pos: np.ndarray
@@ -41,6 +44,11 @@ class StepRecord:
 
 def free_run(system, pos0, seed: int, h: float, n_steps: int, start_step: int = 0,
              mode: str = "lu") -> (List[StepRecord], np.ndarray):
+    """Metropolis steps start_step .. start_step + n_steps - 1 from pos0
+    (Section 2.2): particle g mod n moves to a uniform trial point, the ratio
+    det(A')/det(A) (eq. (detRatioEq)) comes from dense LU or the standard
+    algorithm, and the move is accepted when ratio^2 exceeds the draw.
+    Returns the records and the final positions."""
     n = system.n
     pos = np.array(pos0, dtype=np.float64, copy=True)
     A = slater_dense(pos, system)
@@ -84,7 +92,8 @@ def sweep_energies(system, pos0, seed: int, h: float, sweeps: int, start_step: i
 
 def positions_after(pos0, log):
     """Positions after following a step log (records with particle, new_pos,
-    accepted) from pos0."""
+    accepted) from pos0: an accepted move replaces one particle's position
+    (Section 2.2)."""
     pos = np.array(pos0, dtype=np.float64, copy=True)
     for rec in log:
         if rec.accepted:
@@ -94,6 +103,9 @@ def positions_after(pos0, log):
 
 @dataclasses.dataclass
 class ReplayReport:
+    """What a replay found: per checked step |dln|ratio||, and the counts of
+    trial positions, signs and decisions (Section 2.2's acceptance test) that
+    differ from the log."""
     steps: int = 0
     max_dlog: float = 0.0
     dlogs: list = dataclasses.field(default_factory=list)
@@ -114,7 +126,9 @@ class ReplayReport:
 def replay(system, pos0, seed: int, h: float, log, dec_tol: float = 1e-9,
            mode: str = "lu", check_every: int = 1) -> ReplayReport:
     """Follow a logged run (records with g, particle, new_pos, ratio, accepted),
-    recomputing each move and ratio; the logged decisions are followed.
+    recomputing each move and ratio (Section 2.2, eq. (detRatioEq)); the logged
+    decisions are followed, and a differing decision is classed by whether
+    |ratio^2 - u| exceeds dec_tol (reading R6).
 
     ``check_every`` > 1 computes the oracle ratio only on every k-th step (in
     ``lu`` mode), replaying positions in between."""

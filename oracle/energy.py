@@ -51,19 +51,21 @@ def _lap_from_disp(d: np.ndarray, sig: np.ndarray, system) -> np.ndarray:
 
 
 def laplacian_values(r: np.ndarray, system) -> np.ndarray:
-    """lap phi_j(r) for all orbitals j (zero beyond the cutoff)."""
+    """lap phi_j(r) for all orbitals j (zero beyond the cutoff): the Laplacian of
+    eq. (gaussian)'s orbitals in closed form, as eq. (energyEq) needs it."""
     d = min_image(np.asarray(r, dtype=np.float64)[None, :] - system.sites, system.box)
     return _lap_from_disp(d, system.sigma, system)
 
 
 def laplacian_dense(pos: np.ndarray, system) -> np.ndarray:
-    """Dense Lap[p, j] = lap phi_j(r_p) in original labels."""
+    """Dense Lap[p, j] = lap phi_j(r_p) in original labels (eq. (energyEq))."""
     d = min_image(np.asarray(pos, dtype=np.float64)[:, None, :] - system.sites[None, :, :], system.box)
     return _lap_from_disp(d, system.sigma[None, :], system)
 
 
 def kinetic_terms(pos: np.ndarray, system, particles=None) -> np.ndarray:
-    """t_p = -(1/2) lap_p^T A^{-1} e_p for the given particles (all by default)."""
+    """t_p = -(1/2) lap_p^T A^{-1} e_p for the given particles (all by default):
+    particle p's term of eq. (energyEq) (reading R22), by dense LU."""
     pos = np.asarray(pos, dtype=np.float64)
     n = pos.shape[0]
     ps = np.arange(n) if particles is None else np.asarray(particles, dtype=np.int64)

@@ -26,7 +26,8 @@ from workloads import ORB_GAUSS_PX
 
 
 def min_image(d: np.ndarray, box) -> np.ndarray:
-    """Minimum-image displacement for d in (-L, L): shift by L once if |d| > L/2."""
+    """Minimum-image displacement for d in (-L, L): shift by L once if |d| > L/2
+    (Section 2.1, periodic cube; reading R8)."""
     box = np.asarray(box, dtype=np.float64)
     half = 0.5 * box
     d = np.where(d > half, d - box, d)
@@ -35,13 +36,15 @@ def min_image(d: np.ndarray, box) -> np.ndarray:
 
 
 def dist2(r: np.ndarray, Z: np.ndarray, box) -> np.ndarray:
-    """Squared minimum-image distance between r (...,3) and Z (...,3)."""
+    """Squared minimum-image distance between r (...,3) and Z (...,3), summed as
+    (dx*dx + dy*dy) + dz*dz (reading R8)."""
     d = min_image(r - Z, box)
     return (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
 
 
 def orbital_values(r: np.ndarray, system, cols=None) -> np.ndarray:
-    """phi_j(r) for all orbitals j (or the given subset), zero beyond the cutoff."""
+    """phi_j(r) for all orbitals j (or the given subset), zero beyond the cutoff:
+    the Gaussians of eq. (gaussian), plus the p-like term where the system has it."""
     Z = system.sites if cols is None else system.sites[cols]
     sig = system.sigma if cols is None else system.sigma[cols]
     d = min_image(np.asarray(r, dtype=np.float64)[None, :] - Z, system.box)
@@ -54,13 +57,15 @@ def orbital_values(r: np.ndarray, system, cols=None) -> np.ndarray:
 
 
 def row_pattern(r: np.ndarray, system) -> np.ndarray:
-    """Sorted orbital ids j with |r - Z_j|^2 <= rc^2 (minimum image)."""
+    """Sorted orbital ids j with |r - Z_j|^2 <= rc^2 (minimum image): the nonzero
+    pattern of a Slater row (Section 2.1, truncated orbitals; reading R8)."""
     d2 = dist2(np.asarray(r, dtype=np.float64)[None, :], system.sites, system.box)
     return np.nonzero(d2 <= system.cutoff * system.cutoff)[0]
 
 
 def slater_dense(pos: np.ndarray, system, block: int = 256) -> np.ndarray:
-    """Dense A[p, j] = phi_j(r_p) in original labels (particles x orbitals)."""
+    """Dense A[p, j] = phi_j(r_p) in original labels (particles x orbitals),
+    eq. (SlaterMatrix)."""
     n = pos.shape[0]
     A = np.zeros((n, system.n), dtype=np.float64)
     for p0 in range(0, n, block):

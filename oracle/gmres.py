@@ -27,19 +27,23 @@ from .ilutp import apply_inverse
 
 
 class ProductPreconditioner:
-    """M = (I - zhat_m u_m^T) ... (I - zhat_1 u_1^T) Q (L U)^{-1}."""
+    """M = (I - zhat_m u_m^T) ... (I - zhat_1 u_1^T) Q (L U)^{-1}: the ILUTP
+    preconditioner kept across accepted moves by eqs. (mkp1) and (finalMkm)."""
 
     def __init__(self, L, U, q):
         self.L, self.U, self.q = L, U, q
         self.updates = []   # list of (zhat, u) with u dense
 
     def apply(self, v: np.ndarray) -> np.ndarray:
+        """M v: the factors first, then the updates oldest first (eq. (finalMkm))."""
         y = apply_inverse(self.L, self.U, self.q, v)
         for zhat, u in self.updates:
             y = y - zhat * float(u @ y)
         return y
 
     def add_update(self, z: np.ndarray, u: np.ndarray, ratio: float):
+        """After an accepted move: M <- (I - zhat u^T) M with zhat = z / ratio
+        (eq. (mkp1))."""
         self.updates.append((z / ratio, u.copy()))
 
 

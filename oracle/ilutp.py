@@ -44,11 +44,12 @@ import numpy as np
 
 
 class SingularPivot(Exception):
-    pass
+    """A zero pivot left after the column pivoting of ILUTP."""
 
 
 def paper_lfil(nnz: int, n: int) -> int:
-    """Extra fill per row allowed in L and in U: half the average row count."""
+    """Extra fill per row allowed in L and in U: half the average row count
+    (Section 4's fill rule; reading R14)."""
     return int(math.ceil(nnz / (2.0 * n)))
 
 
@@ -139,7 +140,8 @@ def ilutp(rows, n: int, droptol: float, permtol: float, lfil: int, norm: str = "
 
 
 def dense_factors(L, U, n):
-    """Dense (L, U) with unit diagonal in L."""
+    """Dense (L, U) with unit diagonal in L, from the rows ilutp returns
+    (eq. (ilu): A Q ~ L U)."""
     Ld = np.eye(n)
     Ud = np.zeros((n, n))
     for i in range(n):
@@ -151,12 +153,13 @@ def dense_factors(L, U, n):
 
 
 def rows_from_dense(A: np.ndarray):
+    """The rows of a dense matrix as {column: value} dicts of its nonzeros."""
     return [{int(j): float(A[i, j]) for j in np.nonzero(A[i])[0]} for i in range(A.shape[0])]
 
 
 def apply_inverse(L, U, q, v: np.ndarray) -> np.ndarray:
-    """y = Q (LU)^{-1} v: forward solve with unit L, backward solve with U, then
-    place position c at original column q[c]."""
+    """y = Q (LU)^{-1} v (eq. (ilu)): forward solve with unit L, backward solve
+    with U, then place position c at original column q[c]."""
     n = v.shape[0]
     x = np.array(v, dtype=np.float64, copy=True)
     for i in range(n):

@@ -21,7 +21,9 @@ import scipy.linalg as sla
 
 
 def ratio_lu(A: np.ndarray, p: int, new_row: np.ndarray):
-    """(1 + u^T z, a'^T z) with z = A^{-1} e_p by dense LU with partial pivoting."""
+    """(1 + u^T z, a'^T z) with z = A^{-1} e_p by dense LU with partial pivoting:
+    eq. (detRatioEq) with u = a' - a_p, and the same ratio from the new row
+    alone (reading R7)."""
     n = A.shape[0]
     lu, piv = sla.lu_factor(A, check_finite=False)
     e = np.zeros(n)
@@ -32,7 +34,8 @@ def ratio_lu(A: np.ndarray, p: int, new_row: np.ndarray):
 
 
 def det_leibniz(A: np.ndarray) -> float:
-    """Determinant by the Leibniz permutation sum (tiny n only)."""
+    """Determinant by the Leibniz permutation sum (tiny n only): the definition
+    of det behind eq. (DetRatio)."""
     n = A.shape[0]
     total = 0.0
     for perm in itertools.permutations(range(n)):
@@ -49,7 +52,7 @@ def det_leibniz(A: np.ndarray) -> float:
 
 
 def ratio_leibniz(A: np.ndarray, p: int, new_row: np.ndarray) -> float:
-    """det(A')/det(A) with both determinants by brute force."""
+    """det(A')/det(A) with both determinants by brute force (eq. (DetRatio))."""
     A2 = A.copy()
     A2[p] = new_row
     return det_leibniz(A2) / det_leibniz(A)
@@ -63,13 +66,18 @@ class StandardAlgorithm:
         self.refresh()
 
     def refresh(self):
+        """B = A^{-1} afresh (the standard algorithm recomputes it from time to
+        time to bound the drift of the updates)."""
         self.B = sla.inv(self.A, check_finite=False)
 
     def ratio(self, p: int, new_row: np.ndarray) -> float:
-        # det(A')/det(A) = a'^T A^{-1} e_p  (row p of A' dotted with column p of B)
+        """det(A')/det(A) = a'^T A^{-1} e_p (Section 1)."""
+        # row p of A' dotted with column p of B
         return float(new_row @ self.B[:, p])
 
     def accept(self, p: int, new_row: np.ndarray, ratio: float):
+        """Row p of A becomes new_row; B follows by Sherman-Morrison (Section 1):
+        B <- B - (B e_p)(u^T B) / ratio."""
         u = new_row - self.A[p]
         col = self.B[:, p].copy()
         uB = u @ self.B

@@ -45,6 +45,7 @@ def geometric_reorder(pos: np.ndarray, system):
 
 
 def inverse_perm(perm: np.ndarray) -> np.ndarray:
+    """inv[perm[i]] = i: from position-to-label to label-to-position."""
     inv = np.empty_like(perm)
     inv[perm] = np.arange(perm.shape[0])
     return inv

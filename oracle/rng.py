@@ -43,12 +43,13 @@ def philox4x64_10(counter, key):
 
 def u01(x: int) -> float:
     """Map a 64-bit word to a double in (0,1): the top 52 bits plus one half,
-    scaled by 2^-52.  Every step is exact in binary64, so the value is the same
-    on any IEEE machine; it never equals 0 or 1."""
+    scaled by 2^-52 (reading R1).  Every step is exact in binary64, so the value
+    is the same on any IEEE machine; it never equals 0 or 1."""
     return (float(x >> 12) + 0.5) * TWO_M52
 
 
 def step_draws(seed: int, g: int):
-    """(u_x, u_y, u_z, u_acc) for walker seed ``seed`` at step ``g``."""
+    """(u_x, u_y, u_z, u_acc) for walker seed ``seed`` at step ``g``: the move and
+    the acceptance draw of one Metropolis step (Section 2.2; reading R1)."""
     w = philox4x64_10((g, 0, 0, 0), (seed, 0))
     return tuple(u01(x) for x in w)
