@@ -79,3 +79,18 @@ def test_binding_rejects_mismatched_arrays_before_the_library():
     s2.sigma = np.full(s2.sigma.shape[0] - 1, 0.35)
     with pytest.raises(ValueError):
         vm.Context([s2], [(0, good, 0)], vm.default_params())
+
+
+def test_binding_constants_match_header():
+    """Status codes, precisions and step-record flags of the binding are the
+    header's #define values."""
+    from paper_1008_5113_amd import vmcdet as v
+    with open(os.path.join(ROOT, "include", "vmcdet.h")) as f:
+        defs = dict(re.findall(r"^#define\s+(VMC_\w+)\s+\(?(-?\d+)\)?", f.read(), re.M))
+    names = {k: k for k in ("VMC_OK", "VMC_EINVAL", "VMC_ENOMEM", "VMC_EHIP", "VMC_ENOCONV",
+                            "VMC_ESINGULAR", "VMC_ECAPACITY", "VMC_ESTATE")}
+    names.update({"PREC_FP64": "VMC_PREC_FP64", "PREC_MIXED": "VMC_PREC_MIXED"})
+    names.update({f"FLAG_{k}": f"VMC_FLAG_{k}" for k in ("ACCEPTED", "REORDERED", "REFACTORED",
+                                                         "CONVERGED", "SINGULAR", "CAPACITY")})
+    for py, c in names.items():
+        assert getattr(v, py) == int(defs[c]), (py, c)
