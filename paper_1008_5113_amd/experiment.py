@@ -49,29 +49,47 @@ PHASES = ("prepare", "lsolve", "usolve", "updates", "spmv", "ortho", "solution",
 
 
 def run(K: int, n_walkers: int = 64, sweeps: int = 120, discard: int = 20, keep_walker0: int = 0,
-        step: float = 0.55, permtol: float = 0.5, autotune: bool = True, progress=None) -> dict:
-    """Run the experiment for n = 2K^3; one launch per sweep.  With autotune the
-    refactor period follows the cost balance of Section 3.2 (measured during
-    one extra sweep before the first); keep_walker0 > 0 also returns walker
-    0's step records of the first keep_walker0 sweeps; progress(s) is called
-    after every sweep."""
+        step: float = 0.55, permtol: float = 0.5, autotune: bool = True, progress=None,
+        chunks: int = 1, note=None) -> dict:
+    """Run the experiment for n = 2K^3; `chunks` launches per sweep (one by
+    default).  With autotune the refactor period follows the cost balance of
+    Section 3.2 (measured during one extra sweep before the first);
+    keep_walker0 > 0 also returns walker 0's step records of the first
+    keep_walker0 sweeps; progress(s) is called after every sweep, note(text)
+    after the set-up stages and after every launch."""
     inst = wl.paper_bcc(K=K, n_walkers=n_walkers, step=step, sweeps=sweeps, permtol=permtol)
     n = inst.systems[0].n
+    if not 1 <= chunks <= n:
+        raise ValueError("chunks must lie in [1, n]")
+    say = note or (lambda text: None)
     kw = {"m_max": 200} if autotune else {}
     ctx = Context.from_instance(inst, **kw)
     try:
+        t = time.perf_counter()
         ctx.ilutp(reorder=True)
+        ctx.sync()
+        say(f"n={n}: reorder + ILUTP of {n_walkers} walkers {time.perf_counter() - t:.1f}s")
         if autotune:
+            t = time.perf_counter()
             ctx.autotune(trial_steps=n)
+            say(f"n={n}: autotune (one sweep) {time.perf_counter() - t:.1f}s")
         pos_start = ctx.state(0)["pos"] if keep_walker0 else None
         st0 = ctx.stats()
         energies = np.zeros((n_walkers, sweeps))
         acc = iters = reorders = steps = 0
         kept = []
         t0 = time.perf_counter()
+        bounds = [n * c // chunks for c in range(chunks + 1)]
         for s in range(sweeps):
-            e, log = ctx.run_steps_energy(n, energy_cap=1, log=True)
+            parts = []
+            for c in range(chunks):
+                e, part = ctx.run_steps_energy(bounds[c + 1] - bounds[c], energy_cap=1, log=True)
+                parts.append(part)
+                if chunks > 1:
+                    say(f"sweep {s + 1}: launch {c + 1}/{chunks}")
+            # the energy is sampled once, at the sweep end (the last launch)
             energies[:, s] = e[:, 0]
+            log = np.concatenate(parts, axis=1) if chunks > 1 else parts[0]
             flags = log["flags"]
             acc += int(np.count_nonzero(flags & FLAG_ACCEPTED))
             reorders += int(np.count_nonzero(flags & FLAG_REORDERED))
@@ -136,14 +154,17 @@ def main(argv=None):
     ap.add_argument("--step", type=float, default=0.55)
     ap.add_argument("--permtol", type=float, default=0.5)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--chunks", type=int, default=1,
+                    help="launches per sweep (progress lines in between, for large n)")
     a = ap.parse_args(argv)
     for n in [int(x) for x in a.sizes.split(",")]:
         K = round((n / 2) ** (1.0 / 3.0))
         if 2 * K ** 3 != n:
             raise SystemExit(f"n = {n} is not 2K^3")
         r = run(K, a.walkers, a.sweeps, a.discard, step=a.step, permtol=a.permtol,
-                autotune=not a.no_autotune,
-                progress=lambda s: print(f"sweep {s + 1}/{a.sweeps}", file=sys.stderr, flush=True))
+                autotune=not a.no_autotune, chunks=a.chunks,
+                progress=lambda s: print(f"sweep {s + 1}/{a.sweeps}", file=sys.stderr, flush=True),
+                note=lambda text: print(text, file=sys.stderr, flush=True))
         print(json.dumps(r), flush=True)
 
 
