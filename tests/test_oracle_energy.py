@@ -144,3 +144,10 @@ def test_experiment_tables_match_golden():
     assert sorted(PAPER_TABLES) == sorted(table)
     for n, (es, ss, ep, sp) in table.items():
         assert PAPER_TABLES[n]["energy"] == ep and PAPER_TABLES[n]["energy_sd"] == sp
+
+
+def test_experiment_rejects_bad_chunking_before_any_device_call():
+    from paper_1008_5113_amd import experiment
+    for chunks in (0, 687):
+        with pytest.raises(ValueError):
+            experiment.run(7, n_walkers=1, sweeps=1, chunks=chunks)
