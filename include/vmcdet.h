@@ -234,7 +234,10 @@ vmc_status vmc_det_ratio(void* ctx, const int32_t* walkers, int32_t count,
    decision; NULL applies the Metropolis rule ratio^2 > u_acc with the
    walker's draw (Section 2.2).  On acceptance the row is replaced and the
    preconditioner updated (eq. (mkp1)); after m_max updates it is refactored.
-   accepted_out (host, count, may be NULL) receives the decisions. */
+   accepted_out (host, count, may be NULL) receives the decisions.  A forced
+   acceptance of a move whose ratio is 0 or not finite is not checked: the new
+   Slater matrix would be singular and the update z/ratio undefined, so the
+   caller must not force one (the Metropolis rule never accepts it). */
 vmc_status vmc_accept(void* ctx, const int32_t* walkers, int32_t count,
                       const uint8_t* accept, uint8_t* accepted_out);
 
