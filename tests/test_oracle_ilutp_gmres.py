@@ -192,3 +192,33 @@ def test_stability_study_runs_and_orders_measures():
         n1 = float(f[f.index("N1/|A|") + 1])
         assert its_max < 40 and n1 < 0.1
     assert "rank correlation" in out
+
+
+def test_gmres_is_the_krylov_least_squares_solution():
+    """Textbook properties of full GMRES (x0 = 0) on a random nonsymmetric
+    system, with M = I: after k iterations z_k minimises ||b - A z|| over
+    K_k(A, b) (checked against a least-squares fit on an explicit Krylov
+    basis), the Givens estimate equals the true residual, the residuals never
+    increase, and at k = n the solve is exact."""
+    rng = np.random.default_rng(11)
+    n = 10
+    A = rng.standard_normal((n, n)) + 3.0 * np.eye(n)
+    b = rng.standard_normal(n)
+    ident = lambda v: v  # noqa: E731
+    prev = np.inf
+    for k in range(1, n + 1):
+        z, its, conv, N, res = gmres_right(A, ident, b, 0.0, k)
+        assert its == k
+        true = np.linalg.norm(b - A @ z)
+        assert abs(res - true) <= 1e-10 * np.linalg.norm(b)
+        assert true <= prev * (1 + 1e-12)
+        prev = true
+        K = np.empty((n, k))
+        K[:, 0] = b / np.linalg.norm(b)
+        for j in range(1, k):
+            v = A @ K[:, j - 1]
+            K[:, j] = v / np.linalg.norm(v)
+        c, *_ = np.linalg.lstsq(A @ K, b, rcond=None)
+        best = np.linalg.norm(b - A @ (K @ c))
+        assert abs(true - best) <= 1e-9 * np.linalg.norm(b)
+    assert prev <= 1e-10 * np.linalg.norm(b)
