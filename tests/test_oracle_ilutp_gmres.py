@@ -222,3 +222,33 @@ def test_gmres_is_the_krylov_least_squares_solution():
         best = np.linalg.norm(b - A @ (K @ c))
         assert abs(true - best) <= 1e-9 * np.linalg.norm(b)
     assert prev <= 1e-10 * np.linalg.norm(b)
+
+
+def test_product_preconditioner_keeps_AM_over_several_moves():
+    """With exact solves, every accepted move leaves A M unchanged (eq. (mkp1)
+    applied repeatedly, eq. (finalMkm)): after three moves of different
+    particles A_3 M_3 v = A_0 M_0 v.  Applying the stored factors in the wrong
+    order breaks this."""
+    inst, s, pos, A0, M0 = _setup(droptol=1e-2)
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(s.n)
+    target = A0 @ M0.apply(v)
+    A = A0.copy()
+    M = ProductPreconditioner(M0.L, M0.U, M0.q)
+    for p, dr in ((40, (0.1, -0.2, 0.05)), (41, (-0.15, 0.1, 0.2)), (40, (0.05, 0.05, -0.1))):
+        rnew = (pos[p] + np.array(dr)) % s.box
+        pos[p] = rnew
+        new = orbital_values(rnew, s)
+        u = new - A[p]
+        e = np.zeros(s.n)
+        e[p] = 1.0
+        z = np.linalg.solve(A, e)   # the exact solve
+        ratio = 1.0 + u @ z
+        M.add_update(z, u, ratio)
+        A[p] = new
+    got = A @ M.apply(v)
+    assert np.linalg.norm(got - target) <= 1e-10 * np.linalg.norm(target)
+    # the same updates in reverse order do not keep the product
+    R = ProductPreconditioner(M0.L, M0.U, M0.q)
+    R.updates = list(reversed(M.updates))
+    assert np.linalg.norm(A @ R.apply(v) - target) > 1e-6 * np.linalg.norm(target)
