@@ -94,3 +94,10 @@ def test_binding_constants_match_header():
                                                          "CONVERGED", "SINGULAR", "CAPACITY")})
     for py, c in names.items():
         assert getattr(v, py) == int(defs[c]), (py, c)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """No fallback: loading a library that is not there raises ImportError."""
+    from paper_1008_5113_amd import vmcdet as v
+    with pytest.raises(ImportError):
+        v.load_library(str(tmp_path / "libvmcdet.so"))
