@@ -1,15 +1,19 @@
 """Benchmark: determinant-ratio steps/s of the persistent fused HIP path.
 
-One bench "step" is one Metropolis step of every walker in the batch (proposal,
-Slater row, ILUTP-preconditioned GMRES ratio, decision, row replacement,
-preconditioner update, and any triggered reorder/refactor), i.e. `walkers`
-det-ratio steps.  The timed region is K such steps, run as launches of the
-persistent kernel of `chunk` steps each (by default one launch of K steps),
-bracketed by device synchronisations and timed with events on the stream the
-kernel runs on.  Set-up (context creation, initial reorder and ILUTP) and W
-warm-up steps, launched in the same chunks, are outside the timed region; with
-the default W = K every launch of the kernel has the same size, so a profiler's
-per-launch average is the timed launch's duration.
+One bench step is one launch of the persistent step kernel in which every
+walker of the batch takes ``--block`` Metropolis steps (proposal, Slater row,
+ILUTP-preconditioned GMRES ratio, decision, row replacement, preconditioner
+update, and any triggered reorder/refactor).  The launch is captured once in a
+HIP graph and replayed.  Set-up (context creation, initial reorder and ILUTP),
+the autotuner's trial (one launch of the same size) and W warm-up bench steps
+are untimed; the K timed bench steps are bracketed by device synchronisations
+and timed with events on the stream the kernel runs on, one event pair per
+launch.  Every launch of the step kernel in a run has the same size, so a
+profiler's per-launch average is the timed launches' duration.
+
+After the timed region one more launch of the same size logs walkers 0 and 1
+of each path; the two paths' ratios on those steps are compared with each
+other, and the oracle leg recomputes sampled ones by dense LU.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -60,7 +64,7 @@ def algorithmic_bytes(stats0, stats1, nnz, n, mixed: bool):
     return tot
 
 
-def measured_traffic(path, workload, chunk, walkers, m_max, autotune):
+def measured_traffic(path, workload, launch):
     """HBM bytes per launch of the step kernel from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy
     calibration), or None when that summary was taken on other kernel sources
@@ -71,8 +75,7 @@ def measured_traffic(path, workload, chunk, walkers, m_max, autotune):
         return None
     with open(f) as fh:
         d = json.load(fh)
-    same = (d.get("source_hash") == kernel_source_hash()
-            and d.get("launch") == {"chunk": chunk, "walkers": walkers, "m_max": m_max, "autotune": autotune})
+    same = d.get("source_hash") == kernel_source_hash() and d.get("launch") == launch
     return d["hbm_bytes_per_launch"] if same else None
 
 
@@ -84,7 +87,25 @@ def factor_nnz(ctx, walkers):
     return acc / len(walkers)
 
 
-def run_path(inst, precision, steps, warmup, chunk, walkers, stream_ptr, tune_steps=0, **kw):
+def launch_plan(steps: int, warmup: int, block: int, autotune: bool):
+    """The launches of one path, in order: (role, Metropolis steps per walker).
+    Every launch has the same size, so the kernel's per-launch average under a
+    profiler is the timed launches' duration."""
+    if steps < 1 or warmup < 0 or block < 1:
+        raise ValueError("steps >= 1, warmup >= 0 and block >= 1 are required")
+    plan = []
+    if autotune:
+        plan.append(("autotune", block))
+    plan += [("warmup", block)] * warmup
+    plan += [("timed", block)] * steps
+    plan.append(("logged", block))
+    return plan
+
+
+LOG_WALKERS = 2  # walkers whose records the post-timed launch keeps
+
+
+def run_path(inst, precision, steps, warmup, block, walkers, stream_ptr, autotune=True, **kw):
     import torch
     import paper_1008_5113_amd as vm
     t0 = time.time()
@@ -93,35 +114,40 @@ def run_path(inst, precision, steps, warmup, chunk, walkers, stream_ptr, tune_st
     ctx.sync()
     log(f"precision={precision}: set-up (create + reorder + ILUTP of {len(walkers)} walkers) "
         f"{time.time() - t0:.1f}s")
+    plan = launch_plan(steps, warmup, block, autotune)
     tune = None
-    if tune_steps:
+    if autotune:
         t1 = time.time()
-        tune = ctx.autotune(trial_steps=tune_steps)
-        log(f"precision={precision}: autotune ({tune_steps} trial steps) {time.time() - t1:.1f}s: {tune}")
+        tune = ctx.autotune(trial_steps=block)
+        log(f"precision={precision}: autotune (one trial launch of {block} steps) {time.time() - t1:.1f}s: {tune}")
     if warmup:
         t1 = time.time()
-        for _ in range(warmup // chunk):
-            ctx.run_steps(chunk)
+        for _ in range(warmup):
+            ctx.run_steps(block, graph=True)
         ctx.sync()
-        log(f"precision={precision}: warm-up {warmup} steps {time.time() - t1:.1f}s")
+        log(f"precision={precision}: warm-up {warmup} launches of {block} steps {time.time() - t1:.1f}s")
     s0 = ctx.stats()
-    # every launch of the persistent kernel covers `chunk` steps of every walker;
-    # one event pair per launch, recorded on the stream the kernel runs on
+    # one graph replay per bench step, each covering `block` steps of every
+    # walker; one event pair per launch, recorded on the stream the kernel runs on
     stream = torch.cuda.current_stream()
-    nl = steps // chunk
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(nl + 1)]
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     evs[0].record(stream)
-    for k in range(nl):
-        ctx.run_steps(chunk)
+    for k in range(steps):
+        ctx.run_steps(block, graph=True)
         evs[k + 1].record(stream)
     torch.cuda.synchronize()
-    launch_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(nl)]
-    ms = evs[0].elapsed_time(evs[nl])
+    launch_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(steps)]
+    ms = evs[0].elapsed_time(evs[steps])
     ctx.sync()
     s1 = ctx.stats()
     nnz = factor_nnz(ctx, list(range(min(4, len(walkers)))))
     n = ctx.ns[0]
+    # accuracy sample: one more launch of the same size logging walkers 0..1,
+    # with their positions at its start (untimed)
+    nlog = min(LOG_WALKERS, len(walkers))
+    pos_before = [ctx.state(w)["pos"] for w in range(nlog)]
+    logrec = ctx.run_steps_logged(block, log_walkers=nlog)
     bytes_ = algorithmic_bytes(s0, s1, nnz, n, precision == vm.PREC_MIXED)
     d = lambda k: sum(b[k] - a[k] for a, b in zip(s0, s1))  # noqa: E731
     nsteps = d("steps")
@@ -131,17 +157,35 @@ def run_path(inst, precision, steps, warmup, chunk, walkers, stream_ptr, tune_st
     phase_us = {name: ph[k] / max(1, nsteps) / vm.vmcdet.WALL_CLOCK_HZ * 1e6
                 for k, name in enumerate(vm.vmcdet.PHASE_NAMES)}
     out = dict(
-        ms=ms, launches=nl, launch_ms_avg=float(np.mean(launch_ms)), steps=nsteps, steps_per_s=nsteps / (ms / 1e3),
+        ms=ms, launches=steps, launch_ms_avg=float(np.mean(launch_ms)),
+        launch_ms_minmax=[float(np.min(launch_ms)), float(np.max(launch_ms))],
+        steps=nsteps, steps_per_s=nsteps / (ms / 1e3),
         accept=d("accepted") / max(1, nsteps), iters_per_step=d("iters") / max(1, nsteps),
         inner_per_step=d("inner_solves") / max(1, nsteps), passes_per_step=d("refine_passes") / max(1, nsteps),
         reorders=d("reorders"), refactors=d("refactors"), nonconverged=d("nonconverged"),
         max_N=max(b["max_N"] for b in s1), nnz_per_row=(nnz / n).tolist(),
         phase_us_per_walker_step={k: round(v, 2) for k, v in phase_us.items()},
-        alg_bytes=bytes_, alg_bytes_per_launch=bytes_ / nl, autotune=tune,
+        alg_bytes=bytes_, alg_bytes_per_launch=bytes_ / steps, autotune=tune,
         alg_gbs=bytes_ / (sum(launch_ms) / 1e3) / 1e9,
+        launches_of_step_kernel=len(plan),
         status=[b["status"] for b in s1 if b["status"] != 0][:4])
     ctx.close()
-    return out
+    return out, {"pos0": pos_before, "log": logrec}
+
+
+def path_agreement(la, lb):
+    """Largest |ln|ratio_a| - ln|ratio_b|| over the steps the two paths' logs
+    share with identical proposals (same step, particle and position), and the
+    number of differing decisions among them."""
+    best, diff, cnt = 0.0, 0, 0
+    for ra, rb in zip(la.reshape(-1), lb.reshape(-1)):
+        if ra["step"] != rb["step"] or ra["particle"] != rb["particle"] or \
+                not np.array_equal(ra["new_pos"], rb["new_pos"]):
+            break
+        cnt += 1
+        best = max(best, abs(np.log(abs(ra["ratio"])) - np.log(abs(rb["ratio"]))))
+        diff += int((ra["flags"] & 1) != (rb["flags"] & 1))
+    return {"steps_compared": cnt, "max_dlog": best, "decision_diff": diff}
 
 
 # ---------------------------------------------------------------------------
@@ -151,11 +195,14 @@ def run_path(inst, precision, steps, warmup, chunk, walkers, stream_ptr, tune_st
 def _oracle_worker(args):
     workload, w, steps = args
     from threadpoolctl import threadpool_limits
+    # import every BLAS user first: the limit applies to the libraries loaded
+    # when it is set
+    import scipy.linalg  # noqa: F401
+    import workloads as wl
+    from oracle.geometry import orbital_values, propose, slater_dense
+    from oracle.ratio import StandardAlgorithm
+    from oracle.rng import step_draws
     with threadpool_limits(1):
-        import workloads as wl
-        from oracle.geometry import orbital_values, propose, slater_dense
-        from oracle.ratio import StandardAlgorithm
-        from oracle.rng import step_draws
         inst = wl.WORKLOADS[workload](w + 1)
         s = inst.systems[0]
         wk = inst.walkers[w]
@@ -174,8 +221,32 @@ def _oracle_worker(args):
         return steps, time.perf_counter() - t0
 
 
+def host_cpu():
+    """CPU model and core counts of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity": avail}
+
+
+CPU_PROC_CAP = 16  # worker processes at most (one GPU's share of the host)
+
+
 def cpu_baseline(workload, procs, steps):
     import multiprocessing as mp
+    host = host_cpu()
+    if procs <= 0:
+        procs = max(1, min(CPU_PROC_CAP, host["affinity"]))
     ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
     with ctx.Pool(procs) as pool:
@@ -186,7 +257,41 @@ def cpu_baseline(workload, procs, steps):
     return dict(value=tot / loop, unit="det-ratio steps/s", cores=procs, kind="oracle",
                 sample=f"{workload}: walkers 0..{procs - 1}, {steps} steps each, one process per walker "
                        f"(single-threaded BLAS), standard algorithm (explicit inverse + Sherman-Morrison); "
-                       f"inverse set-up untimed; wall {wall:.1f}s")
+                       f"inverse set-up untimed; wall {wall:.1f}s",
+                host=host)
+
+
+def oracle_accuracy(inst, logged, samples):
+    """|ln|ratio_gpu| - ln|ratio_oracle|| on `samples` evenly spaced steps of
+    each logged walker of each path, the oracle ratio by dense LU of the
+    Slater matrix at the positions the log implies (its start positions and
+    its accepted moves).  Part of the oracle leg."""
+    from oracle.geometry import orbital_values, slater_dense
+    from oracle.ratio import ratio_lu
+    out = {}
+    cache = {}
+    for path, res in logged.items():
+        worst, nchk = 0.0, 0
+        for w, pos0 in enumerate(res["pos0"]):
+            s = inst.system_of(w)
+            recs = res["log"][w]
+            pos = np.array(pos0, dtype=np.float64, copy=True)
+            pick = set(np.linspace(0, len(recs) - 1, samples).round().astype(int).tolist())
+            for k, r in enumerate(recs):
+                p = int(r["particle"])
+                rnew = np.array(r["new_pos"])
+                if k in pick:
+                    key = (w, int(r["step"]), pos.tobytes(), rnew.tobytes())
+                    if key not in cache:
+                        A = slater_dense(pos, s)
+                        cache[key] = ratio_lu(A, p, orbital_values(rnew, s))[0]
+                    ro = cache[key]
+                    worst = max(worst, abs(np.log(abs(r["ratio"])) - np.log(abs(ro))))
+                    nchk += 1
+                if r["flags"] & 1:
+                    pos[p] = rnew
+        out[path] = {"steps_checked": nchk, "max_dlog": worst}
+    return out
 
 
 def copy_rate_gbs(nbytes=1 << 30, reps=5):
@@ -271,10 +376,9 @@ def scaling_point(lattice, n_walkers, stream_ptr, args):
                        wl.Params(step=0.25, mixed=True, m_max=96))
     out = {"workload": inst.name, "n": s.n, "walkers": n_walkers}
     walkers = list(range(n_walkers))
-    steps = args.steps
     for path, prec in (("mixed", vm.PREC_MIXED), ("fp64", vm.PREC_FP64)):
-        r = run_path(inst, prec, steps, args.warmup, steps, walkers, stream_ptr,
-                     tune_steps=steps if args.autotune else 0, **({"m_max": args.m_max} if args.m_max else {}))
+        r, _ = run_path(inst, prec, args.steps, args.warmup, args.block, walkers, stream_ptr,
+                        autotune=bool(args.autotune), **({"m_max": args.m_max} if args.m_max else {}))
         out[path] = {"steps_per_s": r["steps_per_s"], "accept": r["accept"], "iters_per_step": r["iters_per_step"],
                      "alg_gbs": r["alg_gbs"]}
     acc = out["fp64"]["accept"]
@@ -328,9 +432,9 @@ def energy_bench(inst, walkers, stream_ptr, args):
         kw["energy_tol"] = args.energy_tol
     ctx = vm.Context.from_instance(inst, stream=stream_ptr, precision=prec, **kw)
     ctx.ilutp(reorder=True)
-    tune = ctx.autotune(trial_steps=args.steps) if args.autotune else None
+    tune = ctx.autotune(trial_steps=args.block) if args.autotune else None
     if args.warmup:
-        ctx.run_steps(args.warmup)
+        ctx.run_steps(args.warmup * args.block)
     ctx.sync()
     P = args.energy_particles
     stream = torch.cuda.current_stream()
@@ -356,7 +460,7 @@ def energy_bench(inst, walkers, stream_ptr, args):
         "higher_is_better": True, "dtype": "fp32+fp64" if prec == vm.PREC_MIXED else "f64",
         "data": "synthetic",
         "config": {"workload": inst.name, "walkers": len(walkers), "n": n, "particles_per_walker": P,
-                   "warmup_steps": args.warmup, "autotune": bool(args.autotune),
+                   "warmup_steps": args.warmup * args.block, "autotune": bool(args.autotune),
                    "energy_tol": args.energy_tol if args.energy_tol > 0 else "ratio solves'"},
         "iters_per_term": d("iters") / terms, "inner_per_term": d("inner_solves") / terms,
         "refine_per_term": d("refine_passes") / terms, "reorders": d("reorders"),
@@ -368,24 +472,31 @@ def energy_bench(inst, walkers, stream_ptr, args):
     }
 
 
-def main():
+BLOCK = 200       # Metropolis steps of every walker per bench step (one launch)
+STEPS = 20        # timed bench steps
+WARMUP = 5        # untimed bench steps before them
+ORACLE_SAMPLES = 4  # logged steps per walker recomputed by the oracle
+
+
+def parse_args(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=800)
-    ap.add_argument("--warmup", type=int, default=800)
-    ap.add_argument("--chunk", type=int, default=0,
-                    help="steps per launch of the persistent kernel (0: --steps, one timed launch)")
+    ap.add_argument("--steps", type=int, default=STEPS, help="timed bench steps (launches)")
+    ap.add_argument("--warmup", type=int, default=WARMUP, help="untimed bench steps (launches) before them")
+    ap.add_argument("--block", type=int, default=BLOCK,
+                    help="Metropolis steps of every walker per bench step (one launch of the step kernel)")
     ap.add_argument("--workload", default="mixed_n4000")
     ap.add_argument("--walkers", type=int, default=0, help="0: the workload's count")
     ap.add_argument("--paths", default="mixed,fp64")
     ap.add_argument("--m-max", type=int, default=0,
                     help="cap on stored updates (0: the workload's, or 200 when autotuning)")
     ap.add_argument("--autotune", type=int, default=1,
-                    help="1: run the cost-balance autotuner before warm-up, over one launch of --chunk "
-                         "steps (so every launch of the step kernel has the same size); 0: refactor after "
-                         "a fixed m_max updates only")
-    ap.add_argument("--cpu-procs", type=int, default=8)
+                    help="1: run the cost-balance autotuner before warm-up, over one trial launch of --block "
+                         "steps (the same size as every other launch); 0: refactor after a fixed m_max "
+                         "updates only")
+    ap.add_argument("--cpu-procs", type=int, default=0, help="oracle processes (0: the host's cores, at most 16)")
     ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--oracle-samples", type=int, default=ORACLE_SAMPLES)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phases", action="store_true", help="per-phase micro-benchmarks only")
     ap.add_argument("--phase-reps", type=int, default=20)
@@ -402,7 +513,20 @@ def main():
                     help="with --scaling: timed steps of the GPU standard algorithm (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
-    args = ap.parse_args()
+    args = ap.parse_args(argv)
+    if args.steps < 1 or args.warmup < 0 or args.block < 1:
+        ap.error("--steps >= 1, --warmup >= 0 and --block >= 1 are required")
+    if not args.m_max and args.autotune:
+        args.m_max = 200  # a cap only: the tuned cost balance decides when to refactor
+    return args
+
+
+def main(argv=None):
+    args = parse_args(argv)
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: walkers are independent chains, so the benchmark "
+              "measures one GPU's share of them; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
     if args.copy_calibration:
         import torch
         nbytes = 1 << 30
@@ -414,16 +538,6 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}))
         return
-    if args.chunk <= 0:
-        args.chunk = args.steps
-    if not args.m_max and args.autotune:
-        args.m_max = 200  # a cap only: the tuned cost balance decides when to refactor
-    if args.steps % args.chunk or args.warmup % args.chunk:
-        ap.error("--steps and --warmup must be multiples of --chunk")
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: walkers are independent chains, so the benchmark "
-              "measures one GPU's share of them; use --gpus 1", file=sys.stderr)
-        sys.exit(2)
     import torch
     import workloads as wl
     import paper_1008_5113_amd as vm
@@ -445,19 +559,21 @@ def main():
         for path in args.paths.split(","):
             prec = vm.PREC_MIXED if path == "mixed" else vm.PREC_FP64
             kw = {"m_max": args.m_max} if args.m_max else {}
-            res[path] = phase_bench(inst, prec, walkers, stream_ptr, args.phase_reps, args.warmup, **kw)
+            res[path] = phase_bench(inst, prec, walkers, stream_ptr, args.phase_reps, args.warmup * args.block, **kw)
         print(json.dumps({"phases": res, "workload": args.workload, "walkers": nw}))
         return
-    results = {}
+    results, logged = {}, {}
     for path in args.paths.split(","):
         prec = vm.PREC_MIXED if path == "mixed" else vm.PREC_FP64
-        log(f"path {path}: {nw} walkers, n={inst.systems[0].n}, {args.steps} timed steps")
+        log(f"path {path}: {nw} walkers, n={inst.systems[0].n}, {args.steps} timed launches of {args.block} steps")
         kw = {"m_max": args.m_max} if args.m_max else {}
-        results[path] = run_path(inst, prec, args.steps, args.warmup, args.chunk, walkers, stream_ptr,
-                                 tune_steps=args.chunk if args.autotune else 0, **kw)
+        results[path], logged[path] = run_path(inst, prec, args.steps, args.warmup, args.block, walkers,
+                                               stream_ptr, autotune=bool(args.autotune), **kw)
         log(f"path {path}: {json.dumps(results[path])}")
     head = results.get("mixed") or results[next(iter(results))]
     headpath = "mixed" if "mixed" in results else next(iter(results))
+    launch = {"block": args.block, "walkers": nw, "m_max": args.m_max or inst.params.m_max,
+              "autotune": args.autotune}
     out = {
         "metric": METRIC,
         "value": head["steps_per_s"],
@@ -472,20 +588,23 @@ def main():
         "dtype": "f32+f64" if headpath == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": inst.systems[0].n, "walkers": nw,
-                   "refactor": (f"cost balance, autotuned over {args.chunk} trial steps, cap {args.m_max}"
-                                if args.autotune else f"every {args.m_max or inst.params.m_max} updates"),
+                   "step": f"one graph-replayed launch of the step kernel: {args.block} Metropolis steps of "
+                           f"every walker ({args.block * nw} det-ratio steps)",
+                   "refactor": (f"cost balance, autotuned over one trial launch of {args.block} steps, "
+                                f"cap {args.m_max}" if args.autotune
+                                else f"every {args.m_max or inst.params.m_max} updates"),
                    "lattice": "x".join(str(x) for x in inst.systems[0].lattice),
-                   "path": headpath, "step": "one Metropolis step of every walker"},
+                   "path": headpath},
         "paths": results,
     }
     if "mixed" in results and "fp64" in results:
         out["mixed_over_fp64"] = results["mixed"]["steps_per_s"] / results["fp64"]["steps_per_s"]
+        out["mixed_vs_fp64"] = path_agreement(logged["mixed"]["log"], logged["fp64"]["log"])
     out["roofline"] = {"bound": "hbm", "achieved": head["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": head["alg_gbs"] / HBM_PEAK_GBS,
-                       "traffic": measured_traffic(headpath, args.workload, args.chunk, nw,
-                                                   args.m_max or inst.params.m_max, args.autotune),
+                       "traffic": measured_traffic(headpath, args.workload, launch),
                        "kernel": f"k_run<{1 if headpath == 'mixed' else 0}> (persistent fused step kernel), "
-                                 f"{args.chunk} steps x {nw} walkers per launch",
+                                 f"{args.block} steps x {nw} walkers per launch",
                        "launch_ms_avg": head["launch_ms_avg"],
                        "alg_bytes_per_launch": head["alg_bytes_per_launch"]}
     rf = out["roofline"]
@@ -494,8 +613,12 @@ def main():
     rf["copy_gbs"] = copy_rate_gbs()
     log(f"plain 1 GiB device copy: {rf['copy_gbs']:.0f} GB/s (bytes read + written)")
     if not args.no_cpu_baseline:
-        log(f"cpu baseline: {args.cpu_procs} processes x {args.cpu_steps} oracle steps")
+        log(f"cpu baseline: oracle processes x {args.cpu_steps} steps; oracle check of "
+            f"{args.oracle_samples} logged steps per walker")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_procs, args.cpu_steps)
+        acc = oracle_accuracy(inst, logged, args.oracle_samples)
+        out["cpu_baseline"]["ratio_check"] = acc
+        out["dlog_vs_oracle"] = {p: v["max_dlog"] for p, v in acc.items()}
     print(json.dumps(out), flush=True)
 
 

@@ -248,14 +248,16 @@ vmc_status vmc_accept(void* ctx, const int32_t* walkers, int32_t count,
 vmc_status vmc_run_steps(void* ctx, int32_t steps, vmc_step_record* dev_log, int64_t log_cap);
 
 /* vmc_run_steps with steps = sweeps * n of each walker (a sweep moves every
-   particle once); requires all walkers to share n.  Asynchronous. */
+   particle once), issued as a replay of the captured graph of that launch
+   (vmc_run_steps_graph); requires all walkers to share n.  Asynchronous. */
 vmc_status vmc_run_sweeps(void* ctx, int32_t sweeps, vmc_step_record* dev_log, int64_t log_cap);
 
 /* vmc_run_steps replayed from a HIP graph: the first call with a given
-   (steps, dev_log, log_cap) captures the persistent launch on the context's
-   stream into a graph; later calls with the same arguments launch that graph
-   (a different argument set re-captures).  Same results as vmc_run_steps.
-   Asynchronous. */
+   (steps, dev_log, log_cap) records the persistent launch into a graph (on a
+   private stream of the context, so a context on the null stream works too);
+   that call and later calls with the same arguments launch the graph on the
+   context's stream (a different argument set records a new one).  Same
+   results as vmc_run_steps.  Asynchronous. */
 vmc_status vmc_run_steps_graph(void* ctx, int32_t steps, vmc_step_record* dev_log, int64_t log_cap);
 
 /* Kinetic energy (Section 2.3, Local Energy; Section 4, eq. (energyEq)), with

@@ -469,6 +469,7 @@ struct Ctx {
   // graph of the persistent launch and the arguments it was captured with
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  hipStream_t cap_stream = nullptr;
   int g_steps = -1;
   void* g_log = nullptr;
   long long g_cap = -1;
@@ -974,15 +975,18 @@ vmc_status vmc_accept(void* ctx, const int32_t* walkers, int32_t count, const ui
   return walker_errors(c);
 }
 
-static void launch_run(Ctx* c, int steps, vmc_step_record* dev_log, long long cap) {
+static void launch_run(Ctx* c, int steps, vmc_step_record* dev_log, long long cap, hipStream_t stream) {
   c->sm_current = false;
   const int* order = c->use_order ? c->d_order : nullptr;
   if (c->dp.precision == VMC_PREC_FP64)
-    hipLaunchKernelGGL(k_run<VMC_PREC_FP64>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, steps,
+    hipLaunchKernelGGL(k_run<VMC_PREC_FP64>, dim3(c->nw), dim3(NT), c->lds, stream, c->dW, c->dS, c->dp, steps,
                        dev_log, cap, order);
   else
-    hipLaunchKernelGGL(k_run<VMC_PREC_MIXED>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, steps,
+    hipLaunchKernelGGL(k_run<VMC_PREC_MIXED>, dim3(c->nw), dim3(NT), c->lds, stream, c->dW, c->dS, c->dp, steps,
                        dev_log, cap, order);
+}
+static void launch_run(Ctx* c, int steps, vmc_step_record* dev_log, long long cap) {
+  launch_run(c, steps, dev_log, cap, c->stream);
 }
 
 vmc_status vmc_run_steps(void* ctx, int32_t steps, vmc_step_record* dev_log, int64_t log_cap) {
@@ -1001,10 +1005,6 @@ vmc_status vmc_run_steps_graph(void* ctx, int32_t steps, vmc_step_record* dev_lo
   if (steps == 0) return VMC_OK;
   if (vmc_status s = check_sparse(c, nullptr, c->nw)) return s;
   c->sm_current = false;
-  if (!c->stream) {
-    c->err = "vmc_run_steps_graph needs a context created on a non-default stream";
-    return VMC_EINVAL;
-  }
   const long long cap = dev_log ? log_cap : 0;
   if (!c->gexec || c->g_steps != steps || c->g_log != (void*)dev_log || c->g_cap != cap ||
       c->g_order != c->use_order) {
@@ -1012,10 +1012,14 @@ vmc_status vmc_run_steps_graph(void* ctx, int32_t steps, vmc_step_record* dev_lo
     if (c->graph) (void)hipGraphDestroy(c->graph);
     c->gexec = nullptr;
     c->graph = nullptr;
-    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    launch_run(c, steps, dev_log, cap);
+    // the launch is recorded on a private stream (capture is not possible on
+    // the null stream, and recording runs nothing); the graph then runs on
+    // the context's stream
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    launch_run(c, steps, dev_log, cap, c->cap_stream);
     const hipError_t le = hipGetLastError();
-    const hipError_t ee = hipStreamEndCapture(c->stream, &c->graph);
+    const hipError_t ee = hipStreamEndCapture(c->cap_stream, &c->graph);
     HIPCHK(c, le);
     HIPCHK(c, ee);
     HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
@@ -1034,7 +1038,7 @@ vmc_status vmc_run_sweeps(void* ctx, int32_t sweeps, vmc_step_record* dev_log, i
   if (!c->all_same_n) { c->err = "vmc_run_sweeps needs walkers of equal n; use vmc_run_steps"; return VMC_EINVAL; }
   const long long steps = (long long)sweeps * c->hw[0].n;
   if (steps > 0x7fffffffLL) { c->err = "too many steps"; return VMC_EINVAL; }
-  return vmc_run_steps(ctx, (int32_t)steps, dev_log, log_cap);
+  return vmc_run_steps_graph(ctx, (int32_t)steps, dev_log, log_cap);
 }
 
 // Solver parameters of the kinetic-energy solves: the ratio solves' unless
@@ -1487,6 +1491,7 @@ vmc_status vmc_destroy(void* ctx) {
   (void)hipFree(c->d_order);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (void* b : c->sm_bufs) (void)hipFree(b);
   if (c->d_smB) (void)hipFree(c->d_smB);
   if (c->d_nonconv) (void)hipFree(c->d_nonconv);

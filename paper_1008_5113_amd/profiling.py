@@ -221,10 +221,10 @@ def main():
     for k in ("trace", "fetch", "write", "copy_fetch", "copy_write"):
         s.add_argument("--" + k.replace("_", "-"), required=True)
     s.add_argument("--prec", type=int, default=1)
-    s.add_argument("--chunk", type=int, required=True, help="steps per launch in the profiled run")
+    s.add_argument("--block", type=int, required=True, help="steps per launch in the profiled run")
     s.add_argument("--walkers", type=int, required=True)
     s.add_argument("--m-max", type=int, required=True)
-    s.add_argument("--autotune", type=int, required=True, help="autotuner trial steps of the run (0: none)")
+    s.add_argument("--autotune", type=int, required=True, help="1 if the run autotuned (bench.py --autotune)")
     s.add_argument("--out-json", required=True)
     s.add_argument("--out-md", default=None)
     s.add_argument("--commands", default=None, help="text file holding the profiling commands")
@@ -239,7 +239,7 @@ def main():
         return
     if args.cmd != "summarize":
         ap.error("the commands are summarize and phases")
-    launch = {"chunk": args.chunk, "walkers": args.walkers, "m_max": args.m_max, "autotune": args.autotune}
+    launch = {"block": args.block, "walkers": args.walkers, "m_max": args.m_max, "autotune": args.autotune}
     out = summarize(args.trace, args.fetch, args.write, args.copy_fetch, args.copy_write, args.prec, launch)
     with open(args.out_json, "w") as f:
         json.dump(out, f, indent=1)

@@ -360,15 +360,17 @@ class Context:
         self._check(fn(self.h, int(steps), ctypes.c_void_p(log_device_ptr) if log_device_ptr else None,
                        int(log_cap)))
 
-    def run_steps_logged(self, steps: int, graph: bool = False):
-        """Run and return the step log as a numpy structured array [walker, step]."""
+    def run_steps_logged(self, steps: int, graph: bool = False, log_walkers: Optional[int] = None):
+        """Run and return the step log as a numpy structured array [walker, step]
+        of the first log_walkers walkers (all by default)."""
         import torch
-        cap = self.n_walkers * steps
+        nlog = self.n_walkers if log_walkers is None else max(1, min(int(log_walkers), self.n_walkers))
+        cap = nlog * steps
         buf = torch.empty(cap * STEP_RECORD_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
         self.run_steps(steps, buf.data_ptr(), cap, graph=graph)
         self.sync()
         arr = buf.cpu().numpy().view(STEP_RECORD_DTYPE)
-        return arr.reshape(self.n_walkers, steps)
+        return arr.reshape(nlog, steps)
 
     def kinetic_energy(self, walkers=None, p_begin: int = 0, p_end: Optional[int] = None,
                        terms: bool = False):

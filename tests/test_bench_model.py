@@ -30,3 +30,38 @@ def test_mixed_path_bytes_and_walker_sum():
     want = walker(40, 20, 10, 10, 1200) + walker(4, 2, 1, 1, 0)
     got = bench.algorithmic_bytes(s0, s1, (nA, nL, nU), n, mixed=True)
     assert abs(got - want) <= 1e-9 * want
+
+
+def test_driver_command_line_parses_and_plans_equal_launches():
+    # the exact argument list the round-end benchmark uses
+    args = bench.parse_args(["--gpus", "1", "--steps", "20", "--warmup", "5"])
+    assert (args.gpus, args.steps, args.warmup, args.block) == (1, 20, 5, bench.BLOCK)
+    assert args.m_max == 200 and args.autotune == 1
+    plan = bench.launch_plan(args.steps, args.warmup, args.block, bool(args.autotune))
+    roles = [r for r, _ in plan]
+    assert roles.count("autotune") == 1 and roles.count("warmup") == 5 and roles.count("timed") == 20
+    assert roles[-1] == "logged"
+    # every launch of the step kernel has the same size, so a profiler's
+    # per-launch average is the timed launches' duration
+    assert {s for _, s in plan} == {args.block}
+
+
+def test_any_steps_and_warmup_are_accepted():
+    for steps, warmup in [(1, 0), (3, 7), (20, 5), (7, 13)]:
+        args = bench.parse_args(["--steps", str(steps), "--warmup", str(warmup), "--block", "50"])
+        plan = bench.launch_plan(args.steps, args.warmup, args.block, False)
+        assert sum(1 for r, _ in plan if r == "timed") == steps
+        assert sum(1 for r, _ in plan if r == "warmup") == warmup
+
+
+def test_defaults_are_the_driver_shape():
+    args = bench.parse_args([])
+    assert (args.steps, args.warmup) == (bench.STEPS, bench.WARMUP)
+    assert args.cpu_procs == 0   # the host's cores, capped
+
+
+def test_bad_counts_are_refused():
+    import pytest
+    for argv in (["--steps", "0"], ["--warmup", "-1"], ["--block", "0"]):
+        with pytest.raises(SystemExit):
+            bench.parse_args(argv)
