@@ -66,6 +66,14 @@ typedef int32_t vmc_status;
 #define VMC_FLAG_CONVERGED 8     /* the final solve met its tolerance */
 #define VMC_FLAG_SINGULAR 16
 #define VMC_FLAG_CAPACITY 32
+/* Which reorder trigger of Section 4 fired (set together with VMC_FLAG_REORDERED) */
+#define VMC_FLAG_TRIG_N 64         /* effective stability N above n_thresh */
+#define VMC_FLAG_TRIG_NOCONV 128   /* the solve missed its tolerance within gmres_maxit
+                                      (mixed: the first inner solve, or the refinement) */
+#define VMC_FLAG_TRIG_ITERS 256    /* iterations >= iter_factor * running average */
+#define VMC_FLAG_TRIG_FORCED 512   /* force_reorder_every test knob */
+#define VMC_FLAG_NOCONV 1024       /* not converged even after reorder + refactor: the walker
+                                      stops with VMC_ENOCONV */
 
 /* Solver and chain parameters.  Zero-initialise and call vmc_default_params. */
 typedef struct vmc_params {
@@ -106,8 +114,23 @@ typedef struct vmc_params {
                                path's GMRES rtol and the mixed path's refinement tolerance);
                                <= 0: the tolerances of the ratio solves.  A term then errs by
                                at most ||A^{-T} lkin_p|| * energy_tol */
-  int32_t reserved[2];
+  int32_t device_ptrs;      /* nonzero: the array arguments of vmc_det_ratio and vmc_accept
+                               (particle, new_pos, ratio_out, info_out, accept, accepted_out)
+                               are device pointers, the walker list must be NULL (all
+                               walkers, count ignored), and both calls return without
+                               synchronising; walker errors then surface at vmc_sync */
+  int32_t test_knobs;       /* test knobs (0 = off), bits VMC_TEST_*: they force conditions
+                               that the error and trigger paths need, from the host */
 } vmc_params;
+
+/* vmc_params.test_knobs bits */
+#define VMC_TEST_ZERO_RATIO 1      /* vmc_det_ratio reports, and leaves pending, a ratio of
+                                      exactly 0 for every move (exercises the refusal of a
+                                      forced acceptance) */
+#define VMC_TEST_FIRST_SOLVE_ONE_ITER 2  /* the first solve of every step stops after one
+                                      GMRES iteration, so it misses its tolerance and the
+                                      not-converged reorder trigger fires; the solve after the
+                                      reorder runs normally */
 
 /* One walker: its physical system (orbital centres and shapes) and start. */
 typedef struct vmc_walker_init {
@@ -138,12 +161,16 @@ typedef struct vmc_step_record {
   int32_t walker;
   int32_t particle;         /* particle id moved */
   double new_pos[3];
-  double ratio;             /* det A'/det A, FP64 */
+  double ratio;             /* det A'/det A = 1 + u^T z, FP64 (eq. (detRatioEq)) */
+  double log_abs_ratio;     /* ln|ratio| in FP64; -inf for a zero ratio */
   double u_acc;             /* acceptance draw in (0,1) */
   double N;                 /* effective stability of the (last) solve */
-  double resid;             /* final residual norm ||e_i - A z||_2 (estimate in FP64 path) */
+  double resid;             /* final residual norm ||e_i - A z||_2 (mixed: computed in FP64;
+                               FP64 path: the GMRES recurrence estimate) */
   int32_t iters;            /* GMRES iterations of the final solve (all inner solves, mixed) */
   int32_t flags;            /* VMC_FLAG_* */
+  int32_t refinements;      /* mixed: FP64 refinement passes of the final solve; 0 in FP64 */
+  int32_t inner_solves;     /* GMRES solves behind the final ratio (1 + refinements) */
 } vmc_step_record;
 
 /* Host copies of a walker's state (any pointer may be NULL to skip). */
@@ -222,10 +249,21 @@ vmc_status vmc_ilutp(void* ctx, const int32_t* walkers, int32_t count, int32_t r
 
 /* Determinant ratio of a trial move for each listed walker (eq. (detRatioEq)):
    ratio = 1 + u^T z with A z = e_i by preconditioned GMRES, with the reorder
-   triggers of Section 4.  particle / new_pos (host, count and count*3) give
-   the move; NULL draws it from the walker's Philox stream (particle = step mod
-   n).  ratio_out (host, count) and info_out (host, count, may be NULL) receive
-   the results; the move stays pending until vmc_accept. */
+   triggers of Section 4 (N > n_thresh, the solve missing its tolerance within
+   gmres_maxit, or iterations >= iter_factor * running average: reorder,
+   refactor and solve again).  The FP64 path stops GMRES once the residual
+   estimate is below gmres_rtol * min(1, |ratio|), the ratio estimated from the
+   current iterate, so small ratios keep their relative accuracy; the mixed
+   path refines until ||e_i - A z|| <= refine_tol * min(1, |ratio|) in FP64.
+   particle / new_pos (count and count*3) give the move; NULL draws it from the
+   walker's Philox stream (particle = step mod n).  ratio_out (count) and
+   info_out (count, may be NULL) receive the results; the move stays pending
+   until vmc_accept.  Host arrays unless vmc_params.device_ptrs (see there).
+   A walker whose solve still misses its tolerance after the reorder and
+   refactor stops: its status becomes VMC_ENOCONV (returned here, and by
+   vmc_sync and the vmc_run_* paths through vmc_sync), its record carries
+   VMC_FLAG_NOCONV and no move is pending.  vmc_build_slater or vmc_ilutp on the
+   walker clears that status. */
 vmc_status vmc_det_ratio(void* ctx, const int32_t* walkers, int32_t count,
                          const int32_t* particle, const double* new_pos,
                          double* ratio_out, vmc_step_record* info_out);
@@ -235,9 +273,11 @@ vmc_status vmc_det_ratio(void* ctx, const int32_t* walkers, int32_t count,
    walker's draw (Section 2.2).  On acceptance the row is replaced and the
    preconditioner updated (eq. (mkp1)); after m_max updates it is refactored.
    accepted_out (host, count, may be NULL) receives the decisions.  A forced
-   acceptance of a move whose ratio is 0 or not finite is not checked: the new
-   Slater matrix would be singular and the update z/ratio undefined, so the
-   caller must not force one (the Metropolis rule never accepts it). */
+   acceptance of a move whose pending ratio is 0 or not finite (the new Slater
+   matrix would be singular and the update z/ratio undefined) is refused with
+   VMC_ESINGULAR: that walker's move stays pending, so the caller can still
+   reject it; the other listed walkers are processed normally.  The Metropolis
+   rule never accepts such a move. */
 vmc_status vmc_accept(void* ctx, const int32_t* walkers, int32_t count,
                       const uint8_t* accept, uint8_t* accepted_out);
 

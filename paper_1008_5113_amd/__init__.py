@@ -7,10 +7,13 @@ kinetic energy through the same solver run in the HIP library
 """
 from .vmcdet import (Context, STEP_RECORD_DTYPE, VmcError, default_params, params_from_workload,
                      PREC_FP64, PREC_MIXED, FLAG_ACCEPTED, FLAG_REORDERED, FLAG_REFACTORED,
-                     FLAG_CONVERGED, FLAG_SINGULAR, FLAG_CAPACITY, LIB_PATH, load_library, lib,
-                     VMC_ESTATE)
+                     FLAG_CONVERGED, FLAG_SINGULAR, FLAG_CAPACITY, FLAG_TRIG_N, FLAG_TRIG_NOCONV,
+                     FLAG_TRIG_ITERS, FLAG_TRIG_FORCED, FLAG_NOCONV, LIB_PATH, load_library, lib,
+                     VMC_ESTATE, VMC_ENOCONV, VMC_ESINGULAR, VMC_EINVAL)
 
 __all__ = ["Context", "STEP_RECORD_DTYPE", "VmcError", "default_params", "params_from_workload",
            "PREC_FP64", "PREC_MIXED", "FLAG_ACCEPTED", "FLAG_REORDERED", "FLAG_REFACTORED",
-           "FLAG_CONVERGED", "FLAG_SINGULAR", "FLAG_CAPACITY", "VMC_ESTATE", "LIB_PATH",
+           "FLAG_CONVERGED", "FLAG_SINGULAR", "FLAG_CAPACITY", "FLAG_TRIG_N", "FLAG_TRIG_NOCONV",
+           "FLAG_TRIG_ITERS", "FLAG_TRIG_FORCED", "FLAG_NOCONV", "VMC_ESTATE", "VMC_ENOCONV",
+           "VMC_ESINGULAR", "VMC_EINVAL", "LIB_PATH",
            "load_library", "lib"]

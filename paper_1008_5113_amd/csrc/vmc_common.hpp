@@ -14,7 +14,7 @@ namespace vmc {
 // permutations); region B holds reduction slots and GMRES scalars.
 // ---------------------------------------------------------------------------
 struct LdsLayout {
-  size_t regionA, red, hb, cs, sn, gg, rp, yb, gb, cb, sc, ic, stmp, total;
+  size_t regionA, red, hb, cs, sn, gg, rp, yb, ux, gb, cb, sc, ic, stmp, total;
 };
 
 __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -62,6 +62,7 @@ __host__ __device__ inline LdsLayout lds_layout(int n, int ktb, const DevParams&
   L.gg = o; o += (size_t)(maxit + 2) * 8;
   L.rp = o; o += (size_t)maxit * (maxit + 1) / 2 * 8 + 8;
   L.yb = o; o += (size_t)(maxit + 1) * 8;
+  L.ux = o; o += (size_t)(maxit + 1) * 8;
   L.gb = o; o += (size_t)(mmax + 1) * 8;
   L.cb = o; o += (size_t)(mmax + 1) * 8;
   size_t a = o;
@@ -71,7 +72,11 @@ __host__ __device__ inline LdsLayout lds_layout(int n, int ktb, const DevParams&
   if (reo > a) a = reo;
   o = align_up(a, 16);
   L.regionA = 0;
-  L.red = o; o += (size_t)NWAVE * (maxit + 2) * 8;
+  // reduction slots: the Gram-Schmidt dot products (NWAVE per basis vector,
+  // plus the stability term) and, in the factor packing, one int per thread
+  const size_t red_dots = (size_t)NWAVE * (maxit + 2) * 8;
+  const size_t red_scan = (size_t)NT * 4;
+  L.red = o; o += red_dots > red_scan ? red_dots : red_scan;
   L.sc = o; o += 32 * 8;
   L.ic = o; o += 32 * 4;
   L.stmp = o; o += BLK * 8;
@@ -88,6 +93,7 @@ struct Smem {
   double* gg;
   double* rp;
   double* yb;
+  double* ux;
   double* gb;
   double* cb;
   double* sc;
@@ -106,6 +112,7 @@ __device__ inline Smem make_smem(char* base, const LdsLayout& L) {
   s.gg = (double*)(base + L.gg);
   s.rp = (double*)(base + L.rp);
   s.yb = (double*)(base + L.yb);
+  s.ux = (double*)(base + L.ux);
   s.gb = (double*)(base + L.gb);
   s.cb = (double*)(base + L.cb);
   s.sc = (double*)(base + L.sc);

@@ -43,6 +43,11 @@ constexpr int WST_CAPACITY = 1;
 constexpr int WST_SINGULAR = 2;
 constexpr int WST_NOCONV = 4;
 
+// Caller errors of the per-move calls in device-pointer mode (reported and
+// cleared by vmc_sync; they do not stop the walker).
+constexpr int CERR_NOPENDING = 1;   // accept without a pending ratio
+constexpr int CERR_ZERO_RATIO = 2;  // forced acceptance of a zero or non-finite ratio
+
 struct DevParams {
   int precision;
   int maxit;
@@ -59,6 +64,7 @@ struct DevParams {
   // ILUTP per-wave work capacities and concurrent rows (see ilu_default_caps)
   int ilu_hs, ilu_hshift, ilu_nz, ilu_c, ilu_l, ilu_r;
   int ilu_drop_norm;          // 0: tau = droptol*||a_i||_2; 1: droptol*||a_i||_1/nnz(a_i)
+  int test_knobs;             // VMC_TEST_* bits
 };
 
 // Everything the device needs about one walker.  Arrays are per walker; the
@@ -147,7 +153,8 @@ struct WalkerState {
   int m;                      // stored updates
   int status;                 // WST_* bits
   int pend_valid, pend_p, pend_i, pend_newlen, pend_ulen, pend_flags, pend_iters;
-  int pad0;
+  int pend_passes, pend_inner;
+  int call_err;               // CERR_* bits of device-pointer calls since the last vmc_sync
   double pend_newpos[3];
   double pend_ratio, pend_uacc, pend_N, pend_resid;
   double avg_iters;           // running mean of first-solve iteration counts

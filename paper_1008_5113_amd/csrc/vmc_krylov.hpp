@@ -565,10 +565,16 @@ struct SolveOut {
 // and the effective stability N = max_j ||v_j - A M v_j|| (eq.
 // (stabilityVecEq)).  b = e_unit (rhs64 == nullptr) or rhs64 / beta.  The
 // solution is accumulated in FP64: z (+)= scale * sum_j y_j (M v_j).
+// With rel_ulen >= 0 the stop test is relative to the ratio: the iteration
+// stops once the residual estimate is at most tol * min(1, |1 + u^T z_j|), with
+// u the pending update vector (rel_ulen entries) and z_j the current iterate,
+// whose ratio comes from the dots u^T (M v_i) kept per basis vector.  Otherwise
+// it stops at tol (relative to beta).  A breakdown with a singular rotated
+// column (A M singular on the Krylov space) ends the solve unconverged.
 template <typename KT>
 VMC_PHASE SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, Smem& S, int unit,
                                     const double* rhs64, double beta, double tol, int maxit, double* z,
-                                    double scale, bool zinit) {
+                                    double scale, bool zinit, int rel_ulen = -1) {
   const int n = W.n;
   KT* V = (KT*)W.V;
   KT* Xp = (KT*)W.Xp;
@@ -594,6 +600,13 @@ VMC_PHASE SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, Smem& S,
     KT* xp = Xp + (size_t)j * n;
     PhaseClock pc;
     pc.start();
+    if (rel_ulen >= 0 && wave_id() == 0) {
+      // u^T (M v_j) for the ratio of the current iterate (u sparse, FP64)
+      double acc = 0.0;
+      for (int e = lane_id(); e < rel_ulen; e += 64) acc += W.pu_val[e] * (double)xs[W.pu_col[e]];
+      acc = wave_sum(acc);
+      if (lane_id() == 0) S.ux[j] = acc;
+    }
     for (int r = vmc_tid(); r < n; r += NT) xp[r] = xs[r];
     wg_spmv<KT>(W, aval, xs, w);
     __syncthreads();
@@ -641,9 +654,27 @@ VMC_PHASE SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, Smem& S,
       S.gg[j] = c * S.gg[j];
       double* Rc = S.rp + (size_t)j * (j + 1) / 2;
       for (int i = 0; i <= j; ++i) Rc[i] = col[i];
-      const double rj = fabs(S.gg[j + 1]);
+      double rj = fabs(S.gg[j + 1]);
+      int cv = rj <= tol;
+      if (den == 0.0) {
+        // singular rotated column: the residual is still |g_j|, and the
+        // least-squares problem has no solution in this space
+        rj = fabs(S.gg[j]);
+        cv = 0;
+      } else if (cv && rel_ulen >= 0) {
+        // ratio of the current iterate: y = R^{-1} g (k = j + 1), 1 + sum y_i u^T M v_i
+        double* y = S.yb;  // free here: the second Gram-Schmidt pass has been added in
+        double ratio = 1.0;
+        for (int i = j; i >= 0; --i) {
+          double t = S.gg[i];
+          for (int l = i + 1; l <= j; ++l) t -= S.rp[(size_t)l * (l + 1) / 2 + i] * y[l];
+          y[i] = t / S.rp[(size_t)i * (i + 1) / 2 + i];
+          ratio += y[i] * S.ux[i];
+        }
+        cv = rj <= tol * fmin(1.0, fabs(ratio));
+      }
       S.sc[0] = rj;
-      S.ic[2] = (rj <= tol || den == 0.0) ? 1 : 0;
+      S.ic[2] = cv;
       S.ic[3] = (den == 0.0) ? 1 : 0;
     }
     __syncthreads();
@@ -652,7 +683,7 @@ VMC_PHASE SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, Smem& S,
     conv = S.ic[2];
     const int broke = S.ic[3];
     k = broke ? j : j + 1;
-    if (conv) break;
+    if (conv || broke) break;
   }
   // y = R^{-1} g, z (+)= scale * sum y_i Xp_i
   PhaseClock pz;

@@ -100,11 +100,15 @@ struct StepSolve {
 // residual norm without the ratio scale.
 template <int PREC>
 VMC_PHASE StepSolve wg_solve(const Walker& W, int m, const DevParams& P, Smem& S, int i, int ulen,
-                             bool kin = false) {
+                             bool kin = false, int maxit = -1) {
   StepSolve o;
   const double base = kin ? 0.0 : 1.0;
+  if (maxit < 1) maxit = P.maxit;
   if (PREC == VMC_PREC_FP64) {
-    SolveOut g = wg_gmres<double>(W, m, P, S, i, nullptr, 1.0, P.rtol, P.maxit, W.zvec, 1.0, true);
+    // a ratio solve stops relative to min(1, |ratio|); a kinetic term
+    // (base 0) at the absolute tolerance
+    SolveOut g = wg_gmres<double>(W, m, P, S, i, nullptr, 1.0, P.rtol, maxit, W.zvec, 1.0, true,
+                                  kin ? -1 : ulen);
     o.ratio = wg_ratio(W, ulen, W.zvec, S, base);
     o.iters_first = o.iters_total = g.iters;
     o.conv_first = o.conv = g.conv;
@@ -114,7 +118,7 @@ VMC_PHASE StepSolve wg_solve(const Walker& W, int m, const DevParams& P, Smem& S
     o.passes = 0;
   } else {
     // FP32 inner solves, FP64 residual, ratio and monitor (iterative refinement)
-    SolveOut g = wg_gmres<float>(W, m, P, S, i, nullptr, 1.0, P.inner_rtol, P.maxit, W.zvec, 1.0, true);
+    SolveOut g = wg_gmres<float>(W, m, P, S, i, nullptr, 1.0, P.inner_rtol, maxit, W.zvec, 1.0, true);
     o.iters_first = g.iters;
     o.iters_total = g.iters;
     o.conv_first = g.conv;
@@ -224,13 +228,18 @@ VMC_PHASE void wg_det_ratio(const Walker& W, WalkerState* ws, const DevParams& P
   o.inner = o.passes = 0;
   if (st == WST_OK) {
     const int m = ws->m;
-    o = wg_solve<PREC>(W, m, P, S, i, ulen);
+    o = wg_solve<PREC>(W, m, P, S, i, ulen, false, (P.test_knobs & VMC_TEST_FIRST_SOLVE_ONE_ITER) ? 1 : -1);
     const long long g = ws->g;
     const double avg = ws->avg_iters;
     const long long navg = ws->avg_count;
-    bool trig = (o.N > P.n_thresh) || !o.conv_first ||
-                (navg >= P.iter_min_solves && (double)o.iters_first >= P.iter_factor * avg) ||
-                (P.force_reorder_every > 0 && ((g + 1) % P.force_reorder_every) == 0);
+    // the reorder triggers of Section 4; a refinement that misses its
+    // tolerance counts as not converged
+    int why = 0;
+    if (o.N > P.n_thresh) why |= VMC_FLAG_TRIG_N;
+    if (!o.conv_first || !o.conv) why |= VMC_FLAG_TRIG_NOCONV;
+    if (navg >= P.iter_min_solves && (double)o.iters_first >= P.iter_factor * avg) why |= VMC_FLAG_TRIG_ITERS;
+    if (P.force_reorder_every > 0 && ((g + 1) % P.force_reorder_every) == 0) why |= VMC_FLAG_TRIG_FORCED;
+    const bool trig = why != 0;
     __syncthreads();
     if (vmc_tid() == 0) {
       ws->avg_count = navg + 1;
@@ -246,7 +255,7 @@ VMC_PHASE void wg_det_ratio(const Walker& W, WalkerState* ws, const DevParams& P
       ws->st_upd_entries += ent;
     }
     if (trig) {
-      flags |= VMC_FLAG_REORDERED;
+      flags |= VMC_FLAG_REORDERED | why;
       st = wg_reorder_refactor<PREC>(W, P, S);
       if (vmc_tid() == 0) {
         ws->m = 0;
@@ -266,6 +275,12 @@ VMC_PHASE void wg_det_ratio(const Walker& W, WalkerState* ws, const DevParams& P
           ws->st_inner += o.inner;
           ws->st_refine += o.passes;
         }
+        // still not converged with a fresh ordering and factorisation: the
+        // walker stops with VMC_ENOCONV
+        if (!o.conv) {
+          st |= WST_NOCONV;
+          flags |= VMC_FLAG_NOCONV;
+        }
       }
     }
   }
@@ -281,6 +296,8 @@ VMC_PHASE void wg_det_ratio(const Walker& W, WalkerState* ws, const DevParams& P
     ws->pend_ulen = ulen;
     ws->pend_flags = flags;
     ws->pend_iters = o.iters_total;
+    ws->pend_passes = o.passes;
+    ws->pend_inner = o.inner;
     ws->pend_newpos[0] = rnew[0];
     ws->pend_newpos[1] = rnew[1];
     ws->pend_newpos[2] = rnew[2];
@@ -297,6 +314,29 @@ VMC_PHASE void wg_det_ratio(const Walker& W, WalkerState* ws, const DevParams& P
   __threadfence_block();
   __syncthreads();
 }
+
+// The step record of the pending move (walker state after wg_det_ratio).
+__device__ inline void fill_record(vmc_step_record& r, const WalkerState* ws, int widx, double ratio, int flags) {
+  r.step = ws->g;
+  r.walker = widx;
+  r.particle = ws->pend_p;
+  r.new_pos[0] = ws->pend_newpos[0];
+  r.new_pos[1] = ws->pend_newpos[1];
+  r.new_pos[2] = ws->pend_newpos[2];
+  r.ratio = ratio;
+  r.log_abs_ratio = log(fabs(ratio));
+  r.u_acc = ws->pend_uacc;
+  r.N = ws->pend_N;
+  r.resid = ws->pend_resid;
+  r.iters = ws->pend_iters;
+  r.flags = flags;
+  r.refinements = ws->pend_passes;
+  r.inner_solves = ws->pend_inner;
+}
+
+// A move may be committed only with a finite nonzero ratio: otherwise the new
+// Slater matrix is singular and zhat = z / ratio undefined.
+__device__ inline bool ratio_acceptable(double ratio) { return isfinite(ratio) && ratio != 0.0; }
 
 // Commit (accept != 0) or discard the pending move; advance the step counter.
 template <int PREC>
@@ -348,18 +388,7 @@ VMC_PHASE void wg_accept(const Walker& W, WalkerState* ws, const DevParams& P, S
   __syncthreads();
   if (vmc_tid() == 0) {
     if (rec) {
-      rec->step = ws->g;
-      rec->walker = widx;
-      rec->particle = p;
-      rec->new_pos[0] = ws->pend_newpos[0];
-      rec->new_pos[1] = ws->pend_newpos[1];
-      rec->new_pos[2] = ws->pend_newpos[2];
-      rec->ratio = ratio;
-      rec->u_acc = ws->pend_uacc;
-      rec->N = ws->pend_N;
-      rec->resid = ws->pend_resid;
-      rec->iters = ws->pend_iters;
-      rec->flags = flags | ((st & WST_SINGULAR) ? VMC_FLAG_SINGULAR : 0);
+      fill_record(*rec, ws, widx, ratio, flags | ((st & WST_SINGULAR) ? VMC_FLAG_SINGULAR : 0));
     }
     ws->g += 1;
     ws->st_steps += 1;

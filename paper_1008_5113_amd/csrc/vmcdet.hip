@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <type_traits>
 #include <cmath>
 #include <cstdio>
@@ -43,6 +44,9 @@ __global__ void __launch_bounds__(NT) k_setup(const Walker* __restrict__ walkers
   if (threadIdx.x < 32) S.ic[threadIdx.x] = 0;
   __syncthreads();
   int st = WST_OK;
+  // a rebuild or refactor starts the walker afresh: earlier errors are
+  // re-detected if they persist
+  if (threadIdx.x == 0) states[w].status = WST_OK;
   if (mode & MODE_REORDER) wg_reorder(W, S);
   if (mode & (MODE_BUILD | MODE_REORDER)) st |= wg_build_all_rows(W, S);
   PhaseClock pc;
@@ -65,12 +69,14 @@ __global__ void __launch_bounds__(NT) k_setup(const Walker* __restrict__ walkers
   }
 }
 
+// One trial move of each listed walker (list null: walker = block index).
+// ratio_out (may be null) receives the ratios, out the step records.
 template <int PREC>
 __global__ void __launch_bounds__(NT, 4) k_ratio(const Walker* __restrict__ walkers, WalkerState* states,
                                               DevParams P, const int* list, const int* particles,
-                                              const double* newpos, vmc_step_record* out) {
+                                              const double* newpos, vmc_step_record* out, double* ratio_out) {
   extern __shared__ __align__(16) char smem[];
-  const int w = list[blockIdx.x];
+  const int w = list ? list[blockIdx.x] : (int)blockIdx.x;
   const Walker& W = walkers[w];
   WalkerState* ws = states + w;
   Smem S = setup_smem(smem, W, P, PREC == VMC_PREC_FP64 ? 8 : 4);
@@ -80,6 +86,7 @@ __global__ void __launch_bounds__(NT, 4) k_ratio(const Walker* __restrict__ walk
   if (ws->status != WST_OK) {
     if (threadIdx.x == 0) {
       out[blockIdx.x].flags = -1;
+      if (ratio_out) ratio_out[blockIdx.x] = 0.0;
       ws->pend_valid = 0;
     }
     return;
@@ -100,48 +107,47 @@ __global__ void __launch_bounds__(NT, 4) k_ratio(const Walker* __restrict__ walk
   }
   wg_det_ratio<PREC>(W, ws, P, S, p, rnew, u[3]);
   if (threadIdx.x == 0) {
-    vmc_step_record& r = out[blockIdx.x];
-    r.step = g;
-    r.walker = w;
-    r.particle = p;
-    r.new_pos[0] = rnew[0];
-    r.new_pos[1] = rnew[1];
-    r.new_pos[2] = rnew[2];
-    r.ratio = ws->pend_ratio;
-    r.u_acc = u[3];
-    r.N = ws->pend_N;
-    r.resid = ws->pend_resid;
-    r.iters = ws->pend_iters;
-    r.flags = ws->pend_flags;
+    if ((P.test_knobs & VMC_TEST_ZERO_RATIO) && ws->pend_valid) ws->pend_ratio = 0.0;
+    fill_record(out[blockIdx.x], ws, w, ws->pend_ratio, ws->pend_flags);
+    if (ratio_out) ratio_out[blockIdx.x] = ws->pend_ratio;
   }
 }
 
+// Commit or discard the pending move of each listed walker (list null:
+// walker = block index).  err_out[k] (may be null) receives CERR_* bits: no
+// pending move, or a forced acceptance of a zero or non-finite ratio, which
+// is refused with the move left pending.  With sticky set the bits also go to
+// the walker's call_err, for vmc_sync to report.
 template <int PREC>
 __global__ void __launch_bounds__(NT) k_accept(const Walker* __restrict__ walkers, WalkerState* states,
                                                DevParams P, const int* list, const unsigned char* decide,
-                                               unsigned char* accepted_out, int* err_out) {
+                                               unsigned char* accepted_out, int* err_out, int sticky) {
   extern __shared__ __align__(16) char smem[];
-  const int w = list[blockIdx.x];
+  const int w = list ? list[blockIdx.x] : (int)blockIdx.x;
   const Walker& W = walkers[w];
   WalkerState* ws = states + w;
   Smem S = setup_smem(smem, W, P, PREC == VMC_PREC_FP64 ? 8 : 4);
   S.ph = states[w].ph;
   if (threadIdx.x < 32) S.ic[threadIdx.x] = 0;
   __syncthreads();
-  if (!ws->pend_valid) {
+  int err = 0;
+  if (!ws->pend_valid) err = CERR_NOPENDING;
+  else if (decide && decide[blockIdx.x] && !ratio_acceptable(ws->pend_ratio)) err = CERR_ZERO_RATIO;
+  if (err) {
     if (threadIdx.x == 0) {
-      err_out[blockIdx.x] = 1;
-      accepted_out[blockIdx.x] = 0;
+      if (err_out) err_out[blockIdx.x] = err;
+      if (accepted_out) accepted_out[blockIdx.x] = 0;
+      if (sticky) ws->call_err |= err;
     }
     return;
   }
   int acc;
   if (decide) acc = decide[blockIdx.x] ? 1 : 0;
-  else acc = (ws->pend_ratio * ws->pend_ratio > ws->pend_uacc) ? 1 : 0;
+  else acc = (ws->pend_ratio * ws->pend_ratio > ws->pend_uacc && ratio_acceptable(ws->pend_ratio)) ? 1 : 0;
   wg_accept<PREC>(W, ws, P, S, acc, w, nullptr);
   if (threadIdx.x == 0) {
-    accepted_out[blockIdx.x] = (unsigned char)acc;
-    err_out[blockIdx.x] = 0;
+    if (accepted_out) accepted_out[blockIdx.x] = (unsigned char)acc;
+    if (err_out) err_out[blockIdx.x] = 0;
   }
 }
 
@@ -171,7 +177,7 @@ __global__ void __launch_bounds__(NT, 4) k_run(const Walker* __restrict__ walker
     for (int c = 0; c < 3; ++c) rnew[c] = propose_axis(W.pos[3 * p + c], u[c], P.step, W.box[c]);
     wg_det_ratio<PREC>(W, ws, P, S, p, rnew, u[3]);
     if (!ws->pend_valid) break;
-    const int acc = (ws->pend_ratio * ws->pend_ratio > u[3]) ? 1 : 0;
+    const int acc = (ws->pend_ratio * ws->pend_ratio > u[3] && ratio_acceptable(ws->pend_ratio)) ? 1 : 0;
     const long long slot = (long long)w * steps + s;
     vmc_step_record* rec = (log && slot < log_cap) ? log + slot : nullptr;
     wg_accept<PREC>(W, ws, P, S, acc, w, rec);
@@ -330,7 +336,7 @@ __global__ void __launch_bounds__(NT) k_sm_run(const Walker* __restrict__ walker
     }
     __syncthreads();
     const double ratio = sd[0];
-    const int acc = (ratio * ratio > u[3]) ? 1 : 0;
+    const int acc = (ratio * ratio > u[3] && isfinite(ratio) && ratio != 0.0) ? 1 : 0;
     if (acc) {
       for (int j = vmc_tid(); j < n; j += NT) col[j] = B[(size_t)p * ld + j];
       __syncthreads();
@@ -378,11 +384,14 @@ __global__ void __launch_bounds__(NT) k_sm_run(const Walker* __restrict__ walker
         r.new_pos[1] = rnew[1];
         r.new_pos[2] = rnew[2];
         r.ratio = ratio;
+        r.log_abs_ratio = ::log(fabs(ratio));
         r.u_acc = u[3];
         r.N = 0.0;
         r.resid = 0.0;
         r.iters = 0;
         r.flags = (acc ? VMC_FLAG_ACCEPTED : 0) | VMC_FLAG_CONVERGED;
+        r.refinements = 0;
+        r.inner_solves = 0;
       }
       ws->g = g + 1;
       ws->st_steps += 1;
@@ -549,8 +558,43 @@ vmc_status walker_errors(Ctx* c) {
   for (int w = 0; w < c->nw; ++w) {
     if (hs[w].status & WST_CAPACITY) { c->err = "walker " + std::to_string(w) + ": capacity exceeded"; return VMC_ECAPACITY; }
     if (hs[w].status & WST_SINGULAR) { c->err = "walker " + std::to_string(w) + ": singular pivot"; return VMC_ESINGULAR; }
+    if (hs[w].status & WST_NOCONV) {
+      c->err = "walker " + std::to_string(w) + ": GMRES did not converge even after reorder and refactor";
+      return VMC_ENOCONV;
+    }
   }
   return VMC_OK;
+}
+
+// Caller errors recorded by device-pointer calls since the last check; clears them.
+vmc_status call_errors(Ctx* c) {
+  std::vector<WalkerState> hs(c->nw);
+  HIPCHK(c, hipMemcpyAsync(hs.data(), c->dS, sizeof(WalkerState) * c->nw, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  vmc_status first = VMC_OK;
+  bool any = false;
+  for (int w = 0; w < c->nw; ++w) {
+    if (!hs[w].call_err) continue;
+    any = true;
+    if (first == VMC_OK) {
+      if (hs[w].call_err & CERR_NOPENDING) {
+        c->err = "walker " + std::to_string(w) + ": accept without a pending ratio";
+        first = VMC_ESTATE;
+      } else {
+        c->err = "walker " + std::to_string(w) + ": forced acceptance of a zero or non-finite ratio refused";
+        first = VMC_ESINGULAR;
+      }
+    }
+    hs[w].call_err = 0;
+  }
+  if (any) {
+    // only the call_err words change; nothing runs on the stream meanwhile
+    for (int w = 0; w < c->nw; ++w)
+      HIPCHK(c, hipMemcpyAsync((char*)(c->dS + w) + offsetof(WalkerState, call_err), &hs[w].call_err, sizeof(int),
+                               hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return first;
 }
 
 }  // namespace
@@ -613,6 +657,7 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
     return VMC_EINVAL;
   }
   d.ilu_drop_norm = p->ilu_drop_norm;
+  d.test_knobs = p->test_knobs;
   d.ilu_r = ILU_R;
   d.ilu_hs = ILU_DEF_HS;
   d.ilu_nz = ILU_DEF_NZ;
@@ -902,8 +947,22 @@ vmc_status vmc_det_ratio(void* ctx, const int32_t* walkers, int32_t count, const
   Ctx* c = (Ctx*)ctx;
   if (!c || !ratio_out || count < 0) return VMC_EINVAL;
   c->sm_current = false;
-  if (!walkers) count = c->nw;
   if ((particle == nullptr) != (new_pos == nullptr)) { c->err = "particle and new_pos go together"; return VMC_EINVAL; }
+  const bool dev = c->prm.device_ptrs != 0;
+  if (dev) {
+    // device arrays, every walker, no synchronisation
+    if (walkers) { c->err = "device-pointer mode takes every walker (walkers must be NULL)"; return VMC_EINVAL; }
+    if (vmc_status s = check_sparse(c, nullptr, c->nw)) return s;
+    if (c->dp.precision == VMC_PREC_FP64)
+      hipLaunchKernelGGL(k_ratio<VMC_PREC_FP64>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp,
+                         (const int*)nullptr, particle, new_pos, info_out ? info_out : c->d_rec, ratio_out);
+    else
+      hipLaunchKernelGGL(k_ratio<VMC_PREC_MIXED>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp,
+                         (const int*)nullptr, particle, new_pos, info_out ? info_out : c->d_rec, ratio_out);
+    HIPCHK(c, hipGetLastError());
+    return VMC_OK;
+  }
+  if (!walkers) count = c->nw;
   int* dl = nullptr;
   vmc_status s = stage_list(c, walkers, count, &dl);
   if (s) return s;
@@ -925,10 +984,10 @@ vmc_status vmc_det_ratio(void* ctx, const int32_t* walkers, int32_t count, const
   }
   if (c->dp.precision == VMC_PREC_FP64)
     hipLaunchKernelGGL(k_ratio<VMC_PREC_FP64>, dim3(count), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, dl,
-                       particle ? c->d_part : nullptr, particle ? c->d_pos : nullptr, c->d_rec);
+                       particle ? c->d_part : nullptr, particle ? c->d_pos : nullptr, c->d_rec, (double*)nullptr);
   else
     hipLaunchKernelGGL(k_ratio<VMC_PREC_MIXED>, dim3(count), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, dl,
-                       particle ? c->d_part : nullptr, particle ? c->d_pos : nullptr, c->d_rec);
+                       particle ? c->d_part : nullptr, particle ? c->d_pos : nullptr, c->d_rec, (double*)nullptr);
   HIPCHK(c, hipGetLastError());
   std::vector<vmc_step_record> rec(count);
   HIPCHK(c, hipMemcpyAsync(rec.data(), c->d_rec, sizeof(vmc_step_record) * count, hipMemcpyDeviceToHost, c->stream));
@@ -937,11 +996,7 @@ vmc_status vmc_det_ratio(void* ctx, const int32_t* walkers, int32_t count, const
     ratio_out[k] = rec[k].ratio;
     if (info_out) info_out[k] = rec[k];
   }
-  s = walker_errors(c);
-  if (s) return s;
-  for (int k = 0; k < count; ++k)
-    if (!(rec[k].flags & VMC_FLAG_CONVERGED)) { c->err = "GMRES did not converge after reorder"; return VMC_ENOCONV; }
-  return VMC_OK;
+  return walker_errors(c);
 }
 
 vmc_status vmc_accept(void* ctx, const int32_t* walkers, int32_t count, const uint8_t* accept,
@@ -949,6 +1004,19 @@ vmc_status vmc_accept(void* ctx, const int32_t* walkers, int32_t count, const ui
   Ctx* c = (Ctx*)ctx;
   if (!c || count < 0) return VMC_EINVAL;
   c->sm_current = false;
+  const bool dev = c->prm.device_ptrs != 0;
+  if (dev) {
+    if (walkers) { c->err = "device-pointer mode takes every walker (walkers must be NULL)"; return VMC_EINVAL; }
+    if (vmc_status s = check_sparse(c, nullptr, c->nw)) return s;
+    if (c->dp.precision == VMC_PREC_FP64)
+      hipLaunchKernelGGL(k_accept<VMC_PREC_FP64>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp,
+                         (const int*)nullptr, accept, accepted_out, (int*)nullptr, 1);
+    else
+      hipLaunchKernelGGL(k_accept<VMC_PREC_MIXED>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp,
+                         (const int*)nullptr, accept, accepted_out, (int*)nullptr, 1);
+    HIPCHK(c, hipGetLastError());
+    return VMC_OK;
+  }
   if (!walkers) count = c->nw;
   int* dl = nullptr;
   vmc_status s = stage_list(c, walkers, count, &dl);
@@ -959,10 +1027,10 @@ vmc_status vmc_accept(void* ctx, const int32_t* walkers, int32_t count, const ui
   if (accept) HIPCHK(c, hipMemcpyAsync(c->d_dec, accept, count, hipMemcpyHostToDevice, c->stream));
   if (c->dp.precision == VMC_PREC_FP64)
     hipLaunchKernelGGL(k_accept<VMC_PREC_FP64>, dim3(count), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, dl,
-                       accept ? c->d_dec : nullptr, c->d_acc, c->d_err);
+                       accept ? c->d_dec : nullptr, c->d_acc, c->d_err, 0);
   else
     hipLaunchKernelGGL(k_accept<VMC_PREC_MIXED>, dim3(count), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp, dl,
-                       accept ? c->d_dec : nullptr, c->d_acc, c->d_err);
+                       accept ? c->d_dec : nullptr, c->d_acc, c->d_err, 0);
   HIPCHK(c, hipGetLastError());
   std::vector<unsigned char> acc(count);
   std::vector<int> err(count);
@@ -970,8 +1038,18 @@ vmc_status vmc_accept(void* ctx, const int32_t* walkers, int32_t count, const ui
   HIPCHK(c, hipMemcpyAsync(err.data(), c->d_err, sizeof(int) * count, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (accepted_out) std::memcpy(accepted_out, acc.data(), count);
-  for (int k = 0; k < count; ++k)
-    if (err[k]) { c->err = "accept without a pending ratio"; return VMC_ESTATE; }
+  vmc_status first = VMC_OK;
+  for (int k = 0; k < count && first == VMC_OK; ++k) {
+    const int w = walkers ? walkers[k] : k;
+    if (err[k] & CERR_NOPENDING) {
+      c->err = "walker " + std::to_string(w) + ": accept without a pending ratio";
+      first = VMC_ESTATE;
+    } else if (err[k] & CERR_ZERO_RATIO) {
+      c->err = "walker " + std::to_string(w) + ": forced acceptance of a zero or non-finite ratio refused";
+      first = VMC_ESINGULAR;
+    }
+  }
+  if (first != VMC_OK) return first;
   return walker_errors(c);
 }
 
@@ -1386,7 +1464,9 @@ vmc_status vmc_sync(void* ctx) {
   Ctx* c = (Ctx*)ctx;
   if (!c) return VMC_EINVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  return walker_errors(c);
+  const vmc_status ce = call_errors(c);
+  const vmc_status we = walker_errors(c);
+  return we != VMC_OK ? we : ce;
 }
 
 vmc_status vmc_get_dims(void* ctx, int32_t walker, int32_t* n, int32_t* row_cap, int32_t* fact_cap) {
@@ -1462,7 +1542,10 @@ vmc_status vmc_get_stats(void* ctx, vmc_stats* out) {
     o.sum_N = s.st_sumN;
     o.update_entries = s.st_upd_entries;
     o.refactor_cost = s.refactor_cost;
-    o.status = (s.status & WST_CAPACITY) ? VMC_ECAPACITY : (s.status & WST_SINGULAR) ? VMC_ESINGULAR : VMC_OK;
+    o.status = (s.status & WST_CAPACITY)   ? VMC_ECAPACITY
+               : (s.status & WST_SINGULAR) ? VMC_ESINGULAR
+               : (s.status & WST_NOCONV)   ? VMC_ENOCONV
+                                           : VMC_OK;
   }
   return VMC_OK;
 }

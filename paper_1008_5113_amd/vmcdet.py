@@ -34,6 +34,14 @@ FLAG_REFACTORED = 4
 FLAG_CONVERGED = 8
 FLAG_SINGULAR = 16
 FLAG_CAPACITY = 32
+FLAG_TRIG_N = 64
+FLAG_TRIG_NOCONV = 128
+FLAG_TRIG_ITERS = 256
+FLAG_TRIG_FORCED = 512
+FLAG_NOCONV = 1024
+
+TEST_ZERO_RATIO = 1
+TEST_FIRST_SOLVE_ONE_ITER = 2
 
 PHASE_NAMES = ["prepare", "lsolve", "usolve", "updates", "spmv", "ortho", "solution", "resid64",
                "accept", "refactor", "reorder", "launch"]
@@ -72,7 +80,8 @@ class VmcParams(ctypes.Structure):
         ("ilu_work_cap", ctypes.c_int32),
         ("ilu_drop_norm", ctypes.c_int32),
         ("energy_tol", ctypes.c_double),
-        ("reserved", ctypes.c_int32 * 2),
+        ("device_ptrs", ctypes.c_int32),
+        ("test_knobs", ctypes.c_int32),
     ]
 
 
@@ -103,20 +112,24 @@ class VmcStepRecord(ctypes.Structure):
         ("particle", ctypes.c_int32),
         ("new_pos", ctypes.c_double * 3),
         ("ratio", ctypes.c_double),
+        ("log_abs_ratio", ctypes.c_double),
         ("u_acc", ctypes.c_double),
         ("N", ctypes.c_double),
         ("resid", ctypes.c_double),
         ("iters", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("refinements", ctypes.c_int32),
+        ("inner_solves", ctypes.c_int32),
     ]
 
 
 STEP_RECORD_DTYPE = np.dtype([
     ("step", np.int64), ("walker", np.int32), ("particle", np.int32), ("new_pos", np.float64, (3,)),
-    ("ratio", np.float64), ("u_acc", np.float64), ("N", np.float64), ("resid", np.float64),
-    ("iters", np.int32), ("flags", np.int32),
+    ("ratio", np.float64), ("log_abs_ratio", np.float64), ("u_acc", np.float64), ("N", np.float64),
+    ("resid", np.float64), ("iters", np.int32), ("flags", np.int32), ("refinements", np.int32),
+    ("inner_solves", np.int32),
 ])
-assert STEP_RECORD_DTYPE.itemsize == ctypes.sizeof(VmcStepRecord) == 80
+assert STEP_RECORD_DTYPE.itemsize == ctypes.sizeof(VmcStepRecord) == 96
 
 
 class VmcStateView(ctypes.Structure):
@@ -343,6 +356,22 @@ class Context:
         if check:
             self._check(st)
         return ratio, info
+
+    def det_ratio_device(self, ratio_ptr: int, info_ptr: Optional[int] = None,
+                         particle_ptr: Optional[int] = None, new_pos_ptr: Optional[int] = None):
+        """vmc_det_ratio in device-pointer mode (vmc_params.device_ptrs set at
+        creation): every walker, device arrays given by address, no
+        synchronisation (errors surface at sync())."""
+        vp = lambda x: ctypes.c_void_p(x) if x else None  # noqa: E731
+        self._check(lib().vmc_det_ratio(self.h, None, 0, vp(particle_ptr), vp(new_pos_ptr), vp(ratio_ptr),
+                                         vp(info_ptr)))
+
+    def accept_device(self, decisions_ptr: Optional[int] = None, accepted_ptr: Optional[int] = None):
+        """vmc_accept in device-pointer mode: every walker, device arrays by
+        address (uint8 decisions, or None for the Metropolis rule), no
+        synchronisation."""
+        vp = lambda x: ctypes.c_void_p(x) if x else None  # noqa: E731
+        self._check(lib().vmc_accept(self.h, None, 0, vp(decisions_ptr), vp(accepted_ptr)))
 
     def accept(self, walkers=None, decisions=None):
         w, cnt = self._wl(walkers)

@@ -91,7 +91,9 @@ def test_binding_constants_match_header():
                             "VMC_ESINGULAR", "VMC_ECAPACITY", "VMC_ESTATE")}
     names.update({"PREC_FP64": "VMC_PREC_FP64", "PREC_MIXED": "VMC_PREC_MIXED"})
     names.update({f"FLAG_{k}": f"VMC_FLAG_{k}" for k in ("ACCEPTED", "REORDERED", "REFACTORED",
-                                                         "CONVERGED", "SINGULAR", "CAPACITY")})
+                                                         "CONVERGED", "SINGULAR", "CAPACITY", "TRIG_N",
+                                                         "TRIG_NOCONV", "TRIG_ITERS", "TRIG_FORCED",
+                                                         "NOCONV")})
     for py, c in names.items():
         assert getattr(v, py) == int(defs[c]), (py, c)
 
