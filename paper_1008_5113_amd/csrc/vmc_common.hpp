@@ -188,6 +188,12 @@ __device__ inline double readlane_t(double v, int k) { return readlane_d(v, k); 
 __device__ inline float readlane_t(float v, int k) { return readlane_f(v, k); }
 __device__ inline int readlane_t(int v, int k) { return readlane_i(v, k); }
 
+// Marks a point where every lane's preceding memory reads must come before
+// any lane's following writes (one lane updating what all lanes just read).
+// A wave executes in lockstep, so on the device this only keeps the compiler
+// from moving memory operations across it.
+__device__ inline void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+
 // Sum over the 64 lanes; every lane gets the same value (fixed order).
 template <typename T>
 __device__ inline T wave_sum_t(T v) {

@@ -277,6 +277,7 @@ __device__ inline int ilu_add_cands(const Walker& W, IluWave& R, int ncand, bool
     R.cdiag[s] = W.u_diag[p];
     R.clen[s] = (short)W.u_len[p];
   }
+  wave_sync();  // the new entries are in the table before any lane scans it
   return ncand + __popcll(mask);
 }
 
@@ -380,12 +381,13 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
         }
         const int sk = ilu_find(R, R.clab[bslot]);
         const double lik = R.sval[sk] / R.cdiag[bslot];
+        const int ul = R.clen[bslot];
+        wave_sync();  // the candidate's entries are read before any lane updates the row
         if (lane == 0) R.cpos[bslot] = (short)CAND_DONE;
         if (fabs(lik) < tau) continue;
         if (lcount >= cap_l) { status = WST_CAPACITY; break; }
         if (lane == 0) { R.lk[lcount] = (short)best; R.lv[lcount] = lik; }
         ++lcount;
-        const int ul = R.clen[bslot];
         for (int e0 = 0; e0 < ul; e0 += 64) {
           const int e = e0 + lane;
           bool isnew = false, cand = false;
@@ -497,6 +499,7 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
       if (permtol * vmax > fabs(vd) && cmax_pos != i) {
         const int cm = q[cmax_pos];
         dval = vmaxv;
+        wave_sync();  // every lane reads the new diagonal's label before lane 0 swaps it
         if (lane == 0) {
           q[i] = (short)cm;
           q[cmax_pos] = (short)cd;

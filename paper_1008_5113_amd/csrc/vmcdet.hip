@@ -1053,7 +1053,7 @@ vmc_status vmc_accept(void* ctx, const int32_t* walkers, int32_t count, const ui
   return walker_errors(c);
 }
 
-static void launch_run(Ctx* c, int steps, vmc_step_record* dev_log, long long cap, hipStream_t stream) {
+static void launch_run_on(Ctx* c, int steps, vmc_step_record* dev_log, long long cap, hipStream_t stream) {
   c->sm_current = false;
   const int* order = c->use_order ? c->d_order : nullptr;
   if (c->dp.precision == VMC_PREC_FP64)
@@ -1064,7 +1064,7 @@ static void launch_run(Ctx* c, int steps, vmc_step_record* dev_log, long long ca
                        dev_log, cap, order);
 }
 static void launch_run(Ctx* c, int steps, vmc_step_record* dev_log, long long cap) {
-  launch_run(c, steps, dev_log, cap, c->stream);
+  launch_run_on(c, steps, dev_log, cap, c->stream);
 }
 
 vmc_status vmc_run_steps(void* ctx, int32_t steps, vmc_step_record* dev_log, int64_t log_cap) {
@@ -1095,7 +1095,7 @@ vmc_status vmc_run_steps_graph(void* ctx, int32_t steps, vmc_step_record* dev_lo
     // the context's stream
     if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    launch_run(c, steps, dev_log, cap, c->cap_stream);
+    launch_run_on(c, steps, dev_log, cap, c->cap_stream);
     const hipError_t le = hipGetLastError();
     const hipError_t ee = hipStreamEndCapture(c->cap_stream, &c->graph);
     HIPCHK(c, le);
