@@ -32,14 +32,19 @@ VMC_PHASE int wg_build_all_rows(const Walker& W, Smem& S) {
 // Geometric greedy reorder of particles and orbitals (Section 3.1): for each
 // position i, bring the orbital closest to the particle at i to column i; if
 // it already is there, bring the particle closest to that orbital to row i.
-// Starts from the identity labelling; squared minimum-image distances; ties to
-// the first position.  Writes rowperm/rpos and colsite/cpos (reorder order)
+// The pass renumbers the matrix from its current order: the previous
+// reorder's result (reo_row/reo_col, without the factorisation's column
+// pivots; the identity after creation).  Squared minimum-image distances; ties
+// to the first position.  Writes rowperm/rpos and colsite/cpos (reorder order)
 // and reo_row/reo_col.
 VMC_PHASE void wg_reorder(const Walker& W, Smem& S) {
   const int n = W.n;
   short* rp = (short*)S.A;
   short* cp = rp + align_up((size_t)n, 8);
-  for (int k = vmc_tid(); k < n; k += NT) { rp[k] = (short)k; cp[k] = (short)k; }
+  for (int k = vmc_tid(); k < n; k += NT) {
+    rp[k] = (short)W.reo_row[k];
+    cp[k] = (short)W.reo_col[k];
+  }
   __syncthreads();
   for (int i = 0; i < n - 1; ++i) {
     const int pi = rp[i];

@@ -3,8 +3,7 @@
 n = 2K^3 electrons in Gaussian orbitals exp(-k|d|^2), k = 1, on a b.c.c.
 lattice of K^3 cubes of side 2.031; entries below 1e-5 of the largest dropped;
 ILUTP droptol 0.01 (scaled by each row's mean magnitude, as SPARSKIT's ILUTP
-does) with column pivoting (permtol 0.5 by default: see workloads.paper_bcc
-for why not the paper's 0.05); full GMRES with rtol 1e-6 and at most 40
+does) with column pivoting at permtol 0.05; full GMRES with rtol 1e-6 and at most 40
 iterations; reorder when N > 100 or the iterations reach four times their
 average; 120 sweeps with the first 20 discarded; the kinetic energy per
 particle (eq. (energyEq)) sampled at the end of every sweep, here through the
@@ -49,7 +48,7 @@ PHASES = ("prepare", "lsolve", "usolve", "updates", "spmv", "ortho", "solution",
 
 
 def run(K: int, n_walkers: int = 64, sweeps: int = 120, discard: int = 20, keep_walker0: int = 0,
-        step: float = 0.55, permtol: float = 0.5, autotune: bool = True, progress=None,
+        step: float = 0.55, permtol: float = 0.05, autotune: bool = True, progress=None,
         chunks: int = 1, note=None) -> dict:
     """Run the experiment for n = 2K^3; `chunks` launches per sweep (one by
     default).  With autotune the refactor period follows the cost balance of
@@ -152,7 +151,7 @@ def main(argv=None):
     ap.add_argument("--sweeps", type=int, default=120)
     ap.add_argument("--discard", type=int, default=20)
     ap.add_argument("--step", type=float, default=0.55)
-    ap.add_argument("--permtol", type=float, default=0.5)
+    ap.add_argument("--permtol", type=float, default=0.05)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--chunks", type=int, default=1,
                     help="launches per sweep (progress lines in between, for large n)")

@@ -1,9 +1,9 @@
 """The paper's experiment (Section 4) at n = 686 on the GPU, through the C-ABI.
 
 128 walkers, 40 sweeps with the paper's solver settings (FP64, GMRES rtol
-1e-6, ILUTP droptol 0.01, reorder on N > 100 or slow convergence; column
-pivoting at permtol 0.5, see workloads.paper_bcc; refactor period by the cost
-balance), the kinetic energy through the same solver at the end of every sweep.
+1e-6, ILUTP droptol 0.01 and permtol 0.05, reorder on N > 100 or slow
+convergence; refactor period by the cost balance), the kinetic energy through
+the same solver at the end of every sweep.
 
 - The energy averaged over sweeps 20..39 and all walkers agrees with the
   paper's Table "energy" (2.0984, sigma 0.0075) within the two runs'

@@ -106,6 +106,49 @@ def test_reorder_golden_line4():
         assert list(c) == [int(t) for t in col.split()]
 
 
+def test_reorder_golden_line4_from_start_order():
+    """The reorder renumbers the matrix it is given: from a start order other
+    than the identity it swaps from there (hand-worked cases D-F, including a
+    cascade that changes the matching)."""
+    s = _line_system()
+    with open(os.path.join(GOLDEN, "reorder_line4_start.txt")) as f:
+        lines = [ln for ln in f if ln.strip() and not ln.startswith("#")]
+    assert len(lines) == 3
+    for ln in lines:
+        xs, r0, c0, row, col = ln.split("|")
+        xs = [float(t) for t in xs.split()[1:]]
+        pos = np.array([[x, 0.0, 0.0] for x in xs])
+        r0 = [int(t) for t in r0.split()]
+        c0 = [int(t) for t in c0.split()]
+        r, c = geometric_reorder(pos, s, r0, c0)
+        assert list(r) == [int(t) for t in row.split()]
+        assert list(c) == [int(t) for t in col.split()]
+        # the start arrays are not modified
+        assert r0 == [int(t) for t in ln.split("|")[1].split()]
+
+
+def test_reorder_start_order_checks():
+    s = _line_system()
+    pos = np.array([[x, 0.0, 0.0] for x in (0.1, 1.1, 2.1, 3.1)])
+    r, c = geometric_reorder(pos, s, np.arange(4), np.arange(4))
+    assert np.array_equal(r, np.arange(4)) and np.array_equal(c, np.arange(4))
+    with pytest.raises(ValueError):
+        geometric_reorder(pos, s, [0, 0, 1, 2], None)
+
+
+def test_reorder_exact_matching_from_any_start():
+    """Particles exactly on distinct orbitals: every start order ends with each
+    particle on its own orbital (distance zero on the diagonal)."""
+    s = wl.make_system((4, 4, 4), sigma=0.35, cutoff=2.0)
+    rng = np.random.default_rng(5)
+    pi = rng.permutation(s.n)
+    pos = s.sites[pi].copy()
+    for t in range(3):
+        r0, c0 = rng.permutation(s.n), rng.permutation(s.n)
+        row, col = geometric_reorder(pos, s, r0, c0)
+        assert np.array_equal(col, pi[row])
+
+
 def test_reorder_recovers_exact_matching():
     s = wl.make_system((4, 4, 8), sigma=0.35, cutoff=2.0)
     rng = np.random.default_rng(3)
