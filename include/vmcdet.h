@@ -88,12 +88,15 @@ typedef struct vmc_params {
   double iter_factor;       /* reorder when iterations >= factor * running average */
   int32_t iter_min_solves;  /* solves before the iteration average is used */
   double inner_rtol;        /* mixed: inner FP32 solve tolerance */
-  double refine_tol;        /* mixed: stop when ||e_i - A z|| <= tol * min(1, |ratio|) */
+  double refine_tol;        /* mixed: converged when ||e_i - A z|| <= tol; refines on to
+                               tol * min(1, |ratio|) within refine_maxit passes */
   int32_t refine_maxit;     /* mixed: maximum refinement passes */
   double step;              /* proposal half-width h (uniform cube) */
   int32_t row_cap;          /* nonzeros per stored Slater row; <= 0: automatic */
   int32_t force_reorder_every; /* test knob: trigger every k-th step (0 = off) */
-  int32_t pad0;
+  int32_t plain_stop;       /* nonzero: a ratio solve stops once converged (residual at
+                               its tolerance, Section 4's criterion) instead of going on
+                               to the tolerance times min(1, |ratio|) (vmc_det_ratio) */
   double refactor_cost;     /* cost-balance refactor (Section 3.2): refactor once the
                                stored-update vector entries streamed by preconditioner
                                applications since the last factorisation reach this value
@@ -251,10 +254,11 @@ vmc_status vmc_ilutp(void* ctx, const int32_t* walkers, int32_t count, int32_t r
    ratio = 1 + u^T z with A z = e_i by preconditioned GMRES, with the reorder
    triggers of Section 4 (N > n_thresh, the solve missing its tolerance within
    gmres_maxit, or iterations >= iter_factor * running average: reorder,
-   refactor and solve again).  The FP64 path stops GMRES once the residual
-   estimate is below gmres_rtol * min(1, |ratio|), the ratio estimated from the
-   current iterate, so small ratios keep their relative accuracy; the mixed
-   path refines until ||e_i - A z|| <= refine_tol * min(1, |ratio|) in FP64.
+   refactor and solve again).  A solve is converged when its residual is at
+   most its tolerance (gmres_rtol; mixed: ||e_i - A z|| <= refine_tol in FP64);
+   it goes on, within gmres_maxit (mixed: refine_maxit passes), until the
+   residual is at most the tolerance times min(1, |ratio|), the ratio estimated
+   from the current iterate, so that small ratios keep their relative accuracy.
    particle / new_pos (count and count*3) give the move; NULL draws it from the
    walker's Philox stream (particle = step mod n).  ratio_out (count) and
    info_out (count, may be NULL) receive the results; the move stays pending

@@ -65,6 +65,7 @@ struct DevParams {
   int ilu_hs, ilu_hshift, ilu_nz, ilu_c, ilu_l, ilu_r;
   int ilu_drop_norm;          // 0: tau = droptol*||a_i||_2; 1: droptol*||a_i||_1/nnz(a_i)
   int test_knobs;             // VMC_TEST_* bits
+  int plain_stop;             // ratio solves stop at their tolerance (no ratio-relative target)
 };
 
 // Everything the device needs about one walker.  Arrays are per walker; the

@@ -565,12 +565,14 @@ struct SolveOut {
 // and the effective stability N = max_j ||v_j - A M v_j|| (eq.
 // (stabilityVecEq)).  b = e_unit (rhs64 == nullptr) or rhs64 / beta.  The
 // solution is accumulated in FP64: z (+)= scale * sum_j y_j (M v_j).
-// With rel_ulen >= 0 the stop test is relative to the ratio: the iteration
-// stops once the residual estimate is at most tol * min(1, |1 + u^T z_j|), with
-// u the pending update vector (rel_ulen entries) and z_j the current iterate,
-// whose ratio comes from the dots u^T (M v_i) kept per basis vector.  Otherwise
-// it stops at tol (relative to beta).  A breakdown with a singular rotated
-// column (A M singular on the Krylov space) ends the solve unconverged.
+// The solve counts as converged once the residual estimate is at most tol
+// (relative to beta).  With rel_ulen >= 0 it iterates further, until the
+// estimate is at most tol * min(1, |1 + u^T z_j|), with u the pending update
+// vector (rel_ulen entries) and z_j the current iterate, whose ratio comes from
+// the dots u^T (M v_i) kept per basis vector, so that a small ratio keeps its
+// relative accuracy; missing only that target by maxit still counts as
+// converged.  A breakdown with a singular rotated column (A M singular on the
+// Krylov space) ends the solve unconverged.
 template <typename KT>
 VMC_PHASE SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, Smem& S, int unit,
                                     const double* rhs64, double beta, double tol, int maxit, double* z,
@@ -592,7 +594,8 @@ VMC_PHASE SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, Smem& S,
   __syncthreads();
   double N = 0.0;
   int k = 0;
-  int conv = 0;
+  int conv = 0;   // at tol
+  int done = 0;   // at the iteration's target (tol, or the ratio-relative one)
   double res = 1.0;
   for (int j = 0; j < maxit; ++j) {
     const KT* vj = V + (size_t)j * n;
@@ -656,11 +659,12 @@ VMC_PHASE SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, Smem& S,
       for (int i = 0; i <= j; ++i) Rc[i] = col[i];
       double rj = fabs(S.gg[j + 1]);
       int cv = rj <= tol;
+      int dn = cv;
       if (den == 0.0) {
         // singular rotated column: the residual is still |g_j|, and the
         // least-squares problem has no solution in this space
         rj = fabs(S.gg[j]);
-        cv = 0;
+        cv = dn = 0;
       } else if (cv && rel_ulen >= 0) {
         // ratio of the current iterate: y = R^{-1} g (k = j + 1), 1 + sum y_i u^T M v_i
         double* y = S.yb;  // free here: the second Gram-Schmidt pass has been added in
@@ -671,19 +675,21 @@ VMC_PHASE SolveOut wg_gmres(const Walker& W, int m, const DevParams& P, Smem& S,
           y[i] = t / S.rp[(size_t)i * (i + 1) / 2 + i];
           ratio += y[i] * S.ux[i];
         }
-        cv = rj <= tol * fmin(1.0, fabs(ratio));
+        dn = rj <= tol * fmin(1.0, fabs(ratio));
       }
       S.sc[0] = rj;
       S.ic[2] = cv;
       S.ic[3] = (den == 0.0) ? 1 : 0;
+      S.ic[9] = dn;
     }
     __syncthreads();
     pc.stop(S, PH_ORTHO);
     res = S.sc[0];
     conv = S.ic[2];
+    done = S.ic[9];
     const int broke = S.ic[3];
     k = broke ? j : j + 1;
-    if (conv || broke) break;
+    if (done || broke) break;
   }
   // y = R^{-1} g, z (+)= scale * sum y_i Xp_i
   PhaseClock pz;

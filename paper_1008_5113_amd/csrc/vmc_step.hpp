@@ -105,10 +105,10 @@ VMC_PHASE StepSolve wg_solve(const Walker& W, int m, const DevParams& P, Smem& S
   const double base = kin ? 0.0 : 1.0;
   if (maxit < 1) maxit = P.maxit;
   if (PREC == VMC_PREC_FP64) {
-    // a ratio solve stops relative to min(1, |ratio|); a kinetic term
-    // (base 0) at the absolute tolerance
+    // a ratio solve iterates to rtol * min(1, |ratio|) and counts as
+    // converged at rtol; a kinetic term (base 0) stops at rtol
     SolveOut g = wg_gmres<double>(W, m, P, S, i, nullptr, 1.0, P.rtol, maxit, W.zvec, 1.0, true,
-                                  kin ? -1 : ulen);
+                                  (kin || P.plain_stop) ? -1 : ulen);
     o.ratio = wg_ratio(W, ulen, W.zvec, S, base);
     o.iters_first = o.iters_total = g.iters;
     o.conv_first = o.conv = g.conv;
@@ -134,8 +134,16 @@ VMC_PHASE StepSolve wg_solve(const Walker& W, int m, const DevParams& P, Smem& S
       o.ratio = wg_ratio(W, ulen, W.zvec, S, base);
       pc.stop(S, PH_RESID);
       o.res = rn;
-      if (rn <= P.refine_tol * (kin ? 1.0 : fmin(1.0, fabs(o.ratio)))) { o.conv = 1; break; }
-      if (pass >= P.refine_maxit || !(rn > 0.0)) break;
+      if (rn <= P.refine_tol * ((kin || P.plain_stop) ? 1.0 : fmin(1.0, fabs(o.ratio)))) {
+        o.conv = 1;
+        break;
+      }
+      // out of passes short of the ratio-relative target: converged if the
+      // residual meets refine_tol itself
+      if (pass >= P.refine_maxit || !(rn > 0.0)) {
+        o.conv = rn <= P.refine_tol ? 1 : 0;
+        break;
+      }
       ++pass;
       SolveOut c = wg_gmres<float>(W, m, P, S, -1, W.rvec, rn, P.inner_rtol, P.maxit, W.zvec, rn, false);
       o.N = fmax(o.N, c.N);

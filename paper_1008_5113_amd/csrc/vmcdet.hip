@@ -658,6 +658,7 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
   }
   d.ilu_drop_norm = p->ilu_drop_norm;
   d.test_knobs = p->test_knobs;
+  d.plain_stop = p->plain_stop != 0;
   d.ilu_r = ILU_R;
   d.ilu_hs = ILU_DEF_HS;
   d.ilu_nz = ILU_DEF_NZ;

@@ -75,7 +75,7 @@ class VmcParams(ctypes.Structure):
         ("step", ctypes.c_double),
         ("row_cap", ctypes.c_int32),
         ("force_reorder_every", ctypes.c_int32),
-        ("pad0", ctypes.c_int32),
+        ("plain_stop", ctypes.c_int32),
         ("refactor_cost", ctypes.c_double),
         ("ilu_work_cap", ctypes.c_int32),
         ("ilu_drop_norm", ctypes.c_int32),
@@ -239,7 +239,8 @@ def params_from_workload(wp, **kw) -> VmcParams:
                 iter_min_solves=wp.iter_min_solves, inner_rtol=wp.inner_rtol,
                 refine_tol=wp.refine_tol, refine_maxit=wp.refine_maxit, step=wp.step,
                 ilu_work_cap=getattr(wp, "ilu_work_cap", 0),
-                ilu_drop_norm=getattr(wp, "ilu_drop_norm", 0))
+                ilu_drop_norm=getattr(wp, "ilu_drop_norm", 0),
+                plain_stop=int(getattr(wp, "plain_stop", False)))
     base.update(kw)
     return default_params(**base)
 

@@ -78,35 +78,6 @@ def test_reorder_bitexact(vm, lattice, cutoff, kind):
     ctx.close()
 
 
-def test_reorder_chained_bitexact(vm):
-    """A reorder renumbers the current matrix: a second reorder at the same
-    positions, and one after a stretch of steps, start from the order the
-    previous one left (Section 3.1; the oracle is given that order)."""
-    _say("case: chained reorders")
-    inst = wl.small_instance(lattice=(4, 4, 8), cutoff=2.0, n_walkers=2, jitter=0.45)
-    s = inst.systems[0]
-    ctx = vm.Context.from_instance(inst)
-    ctx.ilutp(reorder=True)
-    first = [ctx.state(w) for w in range(2)]
-    ctx.ilutp(reorder=True)
-    for w in range(2):
-        st = ctx.state(w)
-        row, col = geometric_reorder(inst.walkers[w].pos0, s, first[w]["reorder_row"], first[w]["reorder_col"])
-        assert np.array_equal(st["reorder_row"], row) and np.array_equal(st["reorder_col"], col)
-    ctx.run_steps(3 * s.n)
-    ctx.sync()
-    before = [ctx.state(w) for w in range(2)]
-    ctx.ilutp(reorder=True)
-    for w in range(2):
-        st = ctx.state(w)
-        row, col = geometric_reorder(before[w]["pos"], s, before[w]["reorder_row"], before[w]["reorder_col"])
-        assert np.array_equal(st["reorder_row"], row) and np.array_equal(st["reorder_col"], col)
-        # rows in reorder order; columns further permuted by the factorisation's pivots
-        assert np.array_equal(st["row_particle"], row)
-        assert np.array_equal(np.sort(st["col_site"]), np.arange(s.n))
-    ctx.close()
-
-
 def test_reorder_exact_matching_configuration(vm):
     _say("case: reorder exact matching")
     s = wl.make_system((4, 4, 8), cutoff=2.0)
