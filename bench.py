@@ -46,10 +46,14 @@ def log(msg: str):
 # ---------------------------------------------------------------------------
 IDX = 2  # bytes per stored column position
 def algorithmic_bytes(stats0, stats1, nnz, n, mixed: bool):
+    """nnz = (nnz(A), nnz(L), nnz(U)) and n of every walker, or one triple and
+    one n for all of them."""
     sv = 4 if mixed else 8
-    nA, nL, nU = nnz
+    k = len(stats0)
+    ns = [n] * k if np.isscalar(n) else list(n)
+    nnzs = [nnz] * k if np.isscalar(nnz[0]) else list(nnz)
     tot = 0.0
-    for a, b in zip(stats0, stats1):
+    for a, b, n, (nA, nL, nU) in zip(stats0, stats1, ns, nnzs):
         iters = b["iters"] - a["iters"]
         inner = b["inner_solves"] - a["inner_solves"]
         solves = b["solves"] - a["solves"]
@@ -77,6 +81,17 @@ def measured_traffic(path, workload, launch):
         d = json.load(fh)
     same = d.get("source_hash") == kernel_source_hash() and d.get("launch") == launch
     return d["hbm_bytes_per_launch"] if same else None
+
+
+def walker_nnz(ctx, nw: int):
+    """Per-walker (nnz(A), nnz(L), nnz(U)) and n: the mean over up to two
+    walkers of each size (walkers of one size have the same statistics)."""
+    ns = [int(ctx.ns[w]) for w in range(nw)]
+    by_n = {}
+    for w, n in enumerate(ns):
+        by_n.setdefault(n, []).append(w)
+    per = {n: factor_nnz(ctx, ws[:2]) for n, ws in by_n.items()}
+    return [per[n] for n in ns], ns
 
 
 def factor_nnz(ctx, walkers):
@@ -141,6 +156,7 @@ def run_path(inst, precision, steps, warmup, block, walkers, stream_ptr, autotun
     ms = evs[0].elapsed_time(evs[steps])
     ctx.sync()
     s1 = ctx.stats()
+    nnzw, nw_n = walker_nnz(ctx, len(walkers))
     nnz = factor_nnz(ctx, list(range(min(4, len(walkers)))))
     n = ctx.ns[0]
     # accuracy sample: one more launch of the same size logging walkers 0..1,
@@ -148,7 +164,7 @@ def run_path(inst, precision, steps, warmup, block, walkers, stream_ptr, autotun
     nlog = min(LOG_WALKERS, len(walkers))
     pos_before = [ctx.state(w)["pos"] for w in range(nlog)]
     logrec = ctx.run_steps_logged(block, log_walkers=nlog)
-    bytes_ = algorithmic_bytes(s0, s1, nnz, n, precision == vm.PREC_MIXED)
+    bytes_ = algorithmic_bytes(s0, s1, nnzw, nw_n, precision == vm.PREC_MIXED)
     d = lambda k: sum(b[k] - a[k] for a, b in zip(s0, s1))  # noqa: E731
     nsteps = d("steps")
     ph = np.zeros(12)
@@ -204,7 +220,7 @@ def _oracle_worker(args):
     from oracle.rng import step_draws
     with threadpool_limits(1):
         inst = wl.WORKLOADS[workload](w + 1)
-        s = inst.systems[0]
+        s = inst.system_of(w)
         wk = inst.walkers[w]
         pos = wk.pos0.copy()
         sm = StandardAlgorithm(slater_dense(pos, s))
@@ -574,8 +590,11 @@ def main(argv=None):
     headpath = "mixed" if "mixed" in results else next(iter(results))
     launch = {"block": args.block, "walkers": nw, "m_max": args.m_max or inst.params.m_max,
               "autotune": args.autotune}
+    sizes = sorted({s.n for s in inst.systems})
+    metric = METRIC if args.workload == "mixed_n4000" else \
+        f"det-ratio steps/s, {args.workload} (n = {', '.join(map(str, sizes))}) x {nw} walkers; % HBM peak"
     out = {
-        "metric": METRIC,
+        "metric": metric,
         "value": head["steps_per_s"],
         "unit": "det-ratio steps/s",
         "n_gpus": 1,
@@ -587,13 +606,13 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "f32+f64" if headpath == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": inst.systems[0].n, "walkers": nw,
+        "config": {"workload": args.workload, "n": sizes[0] if len(sizes) == 1 else sizes, "walkers": nw,
                    "step": f"one graph-replayed launch of the step kernel: {args.block} Metropolis steps of "
                            f"every walker ({args.block * nw} det-ratio steps)",
                    "refactor": (f"cost balance, autotuned over one trial launch of {args.block} steps, "
                                 f"cap {args.m_max}" if args.autotune
                                 else f"every {args.m_max or inst.params.m_max} updates"),
-                   "lattice": "x".join(str(x) for x in inst.systems[0].lattice),
+                   "lattice": ",".join("x".join(str(x) for x in s.lattice) for s in inst.systems),
                    "path": headpath},
         "paths": results,
     }

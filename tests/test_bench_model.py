@@ -65,3 +65,15 @@ def test_bad_counts_are_refused():
     for argv in (["--steps", "0"], ["--warmup", "-1"], ["--block", "0"]):
         with pytest.raises(SystemExit):
             bench.parse_args(argv)
+
+
+def test_uneven_sizes_sum_per_walker():
+    """Walkers of different n (the uneven batch): the count is the sum of each
+    walker's own count with its own n and factor sizes."""
+    s0 = [_stats(0, 0, 0, 0, 0), _stats(0, 0, 0, 0, 0)]
+    s1 = [_stats(30, 10, 10, 0, 50), _stats(12, 4, 4, 0, 8)]
+    sizes = [(100, (700, 150, 250)), (432, (3000, 700, 900))]
+    want = sum(bench.algorithmic_bytes([a], [b], nnz, n, mixed=False)
+               for a, b, (n, nnz) in zip(s0, s1, sizes))
+    got = bench.algorithmic_bytes(s0, s1, [nnz for _, nnz in sizes], [n for n, _ in sizes], mixed=False)
+    assert got == want
