@@ -527,6 +527,8 @@ def parse_args(argv=None):
                          "beside the HBM bound of the dense standard algorithm")
     ap.add_argument("--dense-steps", type=int, default=100,
                     help="with --scaling: timed steps of the GPU standard algorithm (0: skip)")
+    ap.add_argument("--gather-calibration", action="store_true",
+                    help="random 128-byte-row and 4-byte-word gathers of known size, for the HBM counters")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args(argv)
@@ -543,6 +545,25 @@ def main(argv=None):
         print("bench.py runs on one GPU only: walkers are independent chains, so the benchmark "
               "measures one GPU's share of them; use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.gather_calibration:
+        # gathers whose bytes are known: K random 128-byte lines read whole
+        # (index_select of rows), then one 4-byte word from each of K random
+        # lines (the fetch granularity decides what HBM moves for it)
+        import torch
+        lines, K = (1 << 30) // 128, 1 << 22
+        src = torch.ones(lines, 32, dtype=torch.float32, device="cuda")
+        g = torch.Generator(device="cuda")
+        g.manual_seed(7)
+        idx = torch.randperm(lines, device="cuda", generator=g)[:K].contiguous()
+        flat = src.view(-1)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            rows = torch.index_select(src, 0, idx)
+            words = flat[idx * 32]
+        torch.cuda.synchronize()
+        print(json.dumps({"lines": lines, "gathered_lines": K, "row_bytes": 128, "word_bytes": 4,
+                          "index_bytes": 8, "launches": 3, "check": float(rows.sum() + words.sum())}))
+        return
     if args.copy_calibration:
         import torch
         nbytes = 1 << 30
