@@ -383,11 +383,12 @@ __device__ inline double orbital_kinetic(const Walker& W, double d2, double dx, 
 // Candidates: every site of the cells whose corner lies within
 // cutoff + margin of r, the range stretched down by the largest in-cell site
 // offset.  Entries are written in candidate order to out_col/out_val as
-// column positions cmap[site] (site ids when cmap is null).  Returns the entry
-// count (may exceed cap; entries past cap are not written).
+// column positions cmap[site] (site ids when cmap is null), entry o at
+// out[o * stride].  Returns the entry count (may exceed cap; entries past cap
+// are not written).
 template <typename CT, int KIN = 0>
 __device__ inline int wave_row(const Walker& W, double rx, double ry, double rz, const int* cmap,
-                               CT* out_col, double* out_val, float* out_val32, int cap) {
+                               CT* out_col, double* out_val, float* out_val32, int cap, int stride = 1) {
   const int lane = lane_id();
   const double R = W.cutoff + W.margin;
   const int nb = W.nb;
@@ -425,9 +426,10 @@ __device__ inline int wave_row(const Walker& W, double rx, double ry, double rz,
     if (hit) {
       int o = count + before;
       if (o < cap) {
-        out_col[o] = (CT)(cmap ? cmap[site] : site);
-        out_val[o] = val;
-        if (out_val32) out_val32[o] = (float)val;
+        const size_t so = (size_t)o * stride;
+        out_col[so] = (CT)(cmap ? cmap[site] : site);
+        out_val[so] = val;
+        if (out_val32) out_val32[so] = (float)val;
       }
     }
     count += __popcll(mask);

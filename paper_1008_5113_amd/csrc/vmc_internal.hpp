@@ -99,6 +99,7 @@ struct Walker {
 
   // Slater matrix
   int GAS* a_len;
+  // A in slices of 64 rows: entry e of row i at aidx(W, i, e) (see there)
   unsigned short GAS* a_col;
   double GAS* a_val;
   float GAS* a_val32;
@@ -147,6 +148,16 @@ struct Walker {
   int GAS* pu_col;                // UC
   double GAS* pu_val;             // UC
 };
+
+// Slot of entry e of row i of A: rows are grouped in slices of 64, and a
+// slice stores entry e of its 64 rows together (rows of a slice at
+// consecutive addresses), so a wave reading one entry of each of 64 rows
+// reads one contiguous run.  A slice holds W entries per row.
+constexpr int ASL = 64;
+__host__ __device__ inline size_t aidx(int W, int i, int e) {
+  return ((size_t)(i / ASL) * (size_t)W + (size_t)e) * ASL + (size_t)(i % ASL);
+}
+__host__ __device__ inline size_t a_rows_padded(int n) { return ((size_t)n + ASL - 1) / ASL * ASL; }
 
 // Mutable per-walker scalars, kept apart from the (read-mostly) pointer table.
 struct WalkerState {

@@ -350,138 +350,62 @@ VMC_PHASE void wg_precond(const Walker& W, int m, int mmax, const KT* vin, int u
   pc.stop(S, PH_UPDATES);
 }
 
-// Sparse row dot products for the SpMV: 8 threads per row, each thread owning
-// a contiguous chunk of SPMV_CH entries: 16-bit columns read 4 at a time
-// (8-byte loads), values with 16-byte loads (rows are 64-byte aligned because
-// the row capacity is a multiple of 16).
-constexpr int SPMV_CH = 12;
-
-template <typename VT>
-VMC_PHASE void load_vals4(const VT* p, VT* v);
-template <>
-VMC_PHASE void load_vals4<float>(const float* p, float* v) {
-  const float4 t = *reinterpret_cast<const float4*>(p);
-  v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
-}
-template <>
-VMC_PHASE void load_vals4<double>(const double* p, double* v) {
-  const double2 a = *reinterpret_cast<const double2*>(p);
-  const double2 b = *reinterpret_cast<const double2*>(p + 2);
-  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
-}
-
-// One thread's chunk of a row of A: SPMV_CH column positions (16-bit, packed
-// two per word) and values.  The loads are unconditional, so both rows of a
-// pass are in flight before the first one is consumed; entries at or past the
-// row length are masked at the use.
-template <typename VT>
-struct RowSeg {
-  uint2 c[SPMV_CH / 4];
-  VT v[SPMV_CH];
-};
-
-template <typename VT>
-VMC_PHASE void load_row_seg(RowSeg<VT>& g, const unsigned short* ac, const VT* av, int len, int Wc,
-                            int sub) {
-  const int e0 = sub * SPMV_CH;
-#pragma unroll
-  for (int p = 0; p < SPMV_CH / 4; ++p) {
-    const int e = e0 + 4 * p;
-    // groups past the row length re-read the row start (a line the first
-    // thread reads anyway), so the bytes fetched follow the row lengths
-    const int o = (e < len && e + 4 <= Wc) ? e : 0;
-    g.c[p] = *reinterpret_cast<const uint2*>(ac + o);
-    load_vals4<VT>(av + o, g.v + 4 * p);
-  }
-}
-
-// acc = sum over the thread's chunk of av[e] * x[ac[e]], e < len
-template <typename VT, typename XT, typename AT>
-VMC_PHASE AT row_seg_dot(const RowSeg<VT>& g, int len, int sub, const XT* x) {
-  const int e0 = sub * SPMV_CH;
-  AT acc = 0;
-#pragma unroll
-  for (int p = 0; p < SPMV_CH / 4; ++p) {
-    const unsigned lo = g.c[p].x, hi = g.c[p].y;
-    const int cc[4] = {(int)(lo & 0xFFFFu), (int)(lo >> 16), (int)(hi & 0xFFFFu), (int)(hi >> 16)};
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (e0 + 4 * p + k < len) acc += (AT)g.v[4 * p + k] * (AT)x[cc[k]];
-  }
-  return acc;
-}
-
-// w = A x (x in LDS or global).  A pass covers RP row groups of 64 rows (8
-// threads per row; RP = 1, as registers allow).
-// Passes are software-pipelined in two register sets with fixed roles: the
-// next pass's row chunks are in flight while the current one is consumed, and
-// the row lengths are loaded two passes ahead.  Entries past 8*SPMV_CH (rows
-// longer than the chunks cover) are added by a strided tail loop.  When
-// `resid` is set, writes e_unit - A x instead and returns the partial sum of
-// squares.
+// w = A x (x in LDS or global).  A is stored in slices of 64 rows with entry
+// e of the slice's rows contiguous (aidx), so one wave takes a slice with one
+// lane per row and every load of columns or values is a full contiguous line.
+// A wave walks its slice to the longest row length in it, U entries at a time,
+// with the next U entries in flight while the current ones are consumed;
+// entries at or past a lane's own row length are masked at the use (their
+// loads stay within the slice's row capacity).  When `resid` is set, writes
+// e_unit - A x instead and returns the partial sum of squares.
 template <typename VT, typename XT, typename AT, typename OT>
 VMC_PHASE double wg_rows_apply(const Walker& W, const VT* aval, const XT* x, OT* out, int unit,
                                bool resid) {
-  constexpr int RP = 1;
-  const int n = W.n, Wc = W.W;
-  const int rr = vmc_tid() >> 3, sub = vmc_tid() & 7;
-  constexpr int PSTEP = RP * BLK;
+  constexpr int U = 8;
+  const int n = W.n, Wc = W.W, lane = lane_id();
+  const int nsl = (n + ASL - 1) / ASL;
   double sq = 0.0;
-  auto clamp_row = [&](int r) { return r < n ? r : 0; };
-  struct Pass {
-    RowSeg<VT> g[RP];
-    int len[RP];
-  };
-  auto load_lens = [&](int* ln, int base) {
+  for (int s = wave_id(); s < nsl; s += NWAVE) {
+    const int r = s * ASL + lane;
+    const int len = r < n ? W.a_len[r] : 0;
+    const int wl = -wave_mini(-len);
+    const size_t base = (size_t)s * Wc * ASL + lane;
+    const unsigned short* ac = W.a_col + base;
+    const VT* av = aval + base;
+    int cA[U], cB[U];
+    VT vA[U], vB[U];
+    auto issue = [&](int* c, VT* v, int e0) {
 #pragma unroll
-    for (int j = 0; j < RP; ++j) ln[j] = W.a_len[clamp_row(base + rr + j * BLK)];
-  };
-  auto issue = [&](Pass& P, int base, const int* ln) {
-#pragma unroll
-    for (int j = 0; j < RP; ++j) {
-      const int r = base + rr + j * BLK;
-      P.len[j] = r < n ? ln[j] : 0;
-      const size_t o = (size_t)clamp_row(r) * Wc;
-      load_row_seg<VT>(P.g[j], W.a_col + o, aval + o, P.len[j], Wc, sub);
-    }
-  };
-  auto consume = [&](const Pass& P, int base) {
-#pragma unroll
-    for (int j = 0; j < RP; ++j) {
-      const int r = base + rr + j * BLK;
-      AT acc = row_seg_dot<VT, XT, AT>(P.g[j], P.len[j], sub, x);
-      if (P.len[j] > 8 * SPMV_CH) {
-        const size_t o = (size_t)clamp_row(r) * Wc;
-        for (int e = 8 * SPMV_CH + sub; e < P.len[j]; e += 8)
-          acc += (AT)aval[o + e] * (AT)x[W.a_col[o + e]];
+      for (int u = 0; u < U; ++u) {
+        const size_t e = (size_t)min(e0 + u, Wc - 1) * ASL;
+        c[u] = ac[e];
+        v[u] = av[e];
       }
-      const AT a = sum8(acc);
-      if (sub == 0 && r < n) {
-        if (resid) {
-          const double y = (r == unit ? 1.0 : 0.0) - (double)a;
-          out[r] = (OT)y;
-          sq += y * y;
-        } else {
-          out[r] = (OT)a;
-        }
+    };
+    AT acc = 0;
+    auto consume = [&](const int* c, const VT* v, int e0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (e0 + u < len) acc += (AT)v[u] * (AT)x[c[u]];
+    };
+    issue(cA, vA, 0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) { cB[u] = 0; vB[u] = (VT)0; }
+    for (int e0 = 0; e0 < wl; e0 += 2 * U) {
+      if (e0 + U < wl) issue(cB, vB, e0 + U);
+      consume(cA, vA, e0);
+      if (e0 + 2 * U < wl) issue(cA, vA, e0 + 2 * U);
+      consume(cB, vB, e0 + U);
+    }
+    if (r < n) {
+      if (resid) {
+        const double y = (r == unit ? 1.0 : 0.0) - (double)acc;
+        out[r] = (OT)y;
+        sq += y * y;
+      } else {
+        out[r] = (OT)acc;
       }
     }
-  };
-  int lnA[RP], lnB[RP];
-  load_lens(lnA, 0);
-  load_lens(lnB, PSTEP);
-  Pass PA, PB;
-  issue(PA, 0, lnA);
-  load_lens(lnA, 2 * PSTEP);
-  const int npass = (n + PSTEP - 1) / PSTEP;
-  const int npass2 = (npass + 1) / 2 * 2;
-  for (int p = 0; p < npass2; p += 2) {
-    issue(PB, (p + 1) * PSTEP, lnB);
-    load_lens(lnB, (p + 3) * PSTEP);
-    consume(PA, p * PSTEP);
-    issue(PA, (p + 2) * PSTEP, lnA);
-    load_lens(lnA, (p + 4) * PSTEP);
-    consume(PB, (p + 1) * PSTEP);
   }
   return sq;
 }

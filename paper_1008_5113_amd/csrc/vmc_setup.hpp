@@ -13,8 +13,8 @@ VMC_PHASE int wg_build_all_rows(const Walker& W, Smem& S) {
   for (int i = wave_id(); i < n; i += NWAVE) {
     const int p = W.rowperm[i];
     const double rx = W.pos[3 * p], ry = W.pos[3 * p + 1], rz = W.pos[3 * p + 2];
-    int cnt = wave_row(W, rx, ry, rz, W.cpos, W.a_col + (size_t)i * W.W, W.a_val + (size_t)i * W.W,
-                       W.a_val32 + (size_t)i * W.W, W.W);
+    const size_t a0 = aidx(W.W, i, 0);
+    int cnt = wave_row(W, rx, ry, rz, W.cpos, W.a_col + a0, W.a_val + a0, W.a_val32 + a0, W.W, ASL);
     if (lane_id() == 0) W.a_len[i] = cnt < W.W ? cnt : W.W;
     if (cnt > W.W) bad = 1;
   }
@@ -328,8 +328,8 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
         bool cand = false;
         int c = 0, k = 0;
         if (e < len) {
-          c = W.a_col[(size_t)i * W.W + e];
-          const double v = W.a_val[(size_t)i * W.W + e];
+          c = W.a_col[aidx(W.W, i, e)];
+          const double v = W.a_val[aidx(W.W, i, e)];
           R.slab[e] = (short)c;
           R.sval[e] = v;
           ilu_insert(R, c, e);
@@ -584,8 +584,8 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
     W.u_dinv32[i] = (float)dinv;
     for (int e = 0; e < ul; ++e) uc[e] = pinv[uc[e]];
     const int al = W.a_len[i];
-    unsigned short* ac = W.a_col + (size_t)i * W.W;
-    for (int e = 0; e < al; ++e) ac[e] = (unsigned short)pinv[ac[e]];
+    unsigned short* ac = W.a_col + aidx(W.W, i, 0);
+    for (int e = 0; e < al; ++e) ac[(size_t)e * ASL] = (unsigned short)pinv[ac[(size_t)e * ASL]];
     W.ilu_q[i] = q[i];
   }
   __threadfence_block();

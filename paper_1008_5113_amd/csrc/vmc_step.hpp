@@ -22,8 +22,8 @@ VMC_PHASE int wg_prepare(const Walker& W, Smem& S, int p, const double* rnew) {
   double* nv = (double*)((char*)nc + align_up((size_t)W.W * 4, 16));
   const int lo = W.a_len[i];
   for (int e = vmc_tid(); e < lo; e += NT) {
-    oc[e] = W.a_col[(size_t)i * W.W + e];
-    ov[e] = W.a_val[(size_t)i * W.W + e];
+    oc[e] = W.a_col[aidx(W.W, i, e)];
+    ov[e] = W.a_val[aidx(W.W, i, e)];
   }
   if (wave_id() == 0) {
     const int lane = lane_id();
@@ -360,10 +360,11 @@ VMC_PHASE void wg_accept(const Walker& W, WalkerState* ws, const DevParams& P, S
   if (accept) {
     flags |= VMC_FLAG_ACCEPTED;
     for (int e = vmc_tid(); e < newlen; e += NT) {
-      W.a_col[(size_t)i * W.W + e] = (unsigned short)W.new_col[e];
+      const size_t o = aidx(W.W, i, e);
+      W.a_col[o] = (unsigned short)W.new_col[e];
       const double v = W.new_val[e];
-      W.a_val[(size_t)i * W.W + e] = v;
-      W.a_val32[(size_t)i * W.W + e] = (float)v;
+      W.a_val[o] = v;
+      W.a_val32[o] = (float)v;
     }
     if (vmc_tid() == 0) {
       W.a_len[i] = newlen;

@@ -754,7 +754,8 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
     size_t o_sites = add(nn * 3 * 8), o_sigma = add(nn * 8), o_pos = add(nn * 3 * 8);
     size_t o_rowperm = add(nn * 4), o_rpos = add(nn * 4), o_cpos = add(nn * 4), o_colsite = add(nn * 4);
     size_t o_reo_row = add(nn * 4), o_reo_col = add(nn * 4);
-    size_t o_alen = add(nn * 4), o_acol = add(nn * Wc * 2), o_aval = add(nn * Wc * 8), o_aval32 = add(nn * Wc * 4);
+    const size_t na = a_rows_padded(n);  // A's rows, padded to whole slices
+    size_t o_alen = add(nn * 4), o_acol = add(na * Wc * 2), o_aval = add(na * Wc * 8), o_aval32 = add(na * Wc * 4);
     const size_t F = W.F;
     size_t o_llen = add(nn * 4), o_lcol = add(nn * F * 4), o_lval = add(nn * F * 8);
     size_t o_ulen = add(nn * 4), o_ucol = add(nn * F * 4), o_uval = add(nn * F * 8), o_udiag = add(nn * 8);
@@ -1495,12 +1496,23 @@ vmc_status vmc_get_state(void* ctx, int32_t walker, const vmc_state_view* v) {
   HIPCHK(c, cp(v->reorder_row, (const void*)W.reo_row, n * 4));
   HIPCHK(c, cp(v->reorder_col, (const void*)W.reo_col, n * 4));
   HIPCHK(c, cp(v->a_len, (const void*)W.a_len, n * 4));
-  if (v->a_col) {  // stored as 16-bit column positions, exported as int32
-    std::vector<unsigned short> tmp(n * (size_t)W.W);
-    HIPCHK(c, cp(tmp.data(), (const void*)W.a_col, n * W.W * 2));
-    for (size_t e = 0; e < tmp.size(); ++e) v->a_col[e] = tmp[e];
+  {
+    // A is stored in slices of 64 rows (aidx) with 16-bit column positions;
+    // exported row-major, n x W, columns as int32
+    const size_t na = a_rows_padded(n);
+    if (v->a_col) {
+      std::vector<unsigned short> tmp(na * (size_t)W.W);
+      HIPCHK(c, cp(tmp.data(), (const void*)W.a_col, na * W.W * 2));
+      for (int i = 0; i < n; ++i)
+        for (int e = 0; e < W.W; ++e) v->a_col[(size_t)i * W.W + e] = tmp[aidx(W.W, i, e)];
+    }
+    if (v->a_val) {
+      std::vector<double> tmp(na * (size_t)W.W);
+      HIPCHK(c, cp(tmp.data(), (const void*)W.a_val, na * W.W * 8));
+      for (int i = 0; i < n; ++i)
+        for (int e = 0; e < W.W; ++e) v->a_val[(size_t)i * W.W + e] = tmp[aidx(W.W, i, e)];
+    }
   }
-  HIPCHK(c, cp(v->a_val, (const void*)W.a_val, n * W.W * 8));
   HIPCHK(c, cp(v->l_len, (const void*)W.l_len, n * 4));
   HIPCHK(c, cp(v->l_col, (const void*)W.l_col, n * W.F * 4));
   HIPCHK(c, cp(v->l_val, (const void*)W.l_val, n * W.F * 8));
