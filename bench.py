@@ -172,13 +172,19 @@ def run_path(inst, precision, steps, warmup, block, walkers, stream_ptr, autotun
         ph += np.array(b["phase_ticks"], dtype=np.float64) - np.array(a["phase_ticks"], dtype=np.float64)
     phase_us = {name: ph[k] / max(1, nsteps) / vm.vmcdet.WALL_CLOCK_HZ * 1e6
                 for k, name in enumerate(vm.vmcdet.PHASE_NAMES)}
+    # spread of the walkers' own time in the timed launches (the launch ends
+    # with its slowest walker)
+    kl = vm.vmcdet.PHASE_NAMES.index("launch")
+    wt = np.array([b["phase_ticks"][kl] - a["phase_ticks"][kl] for a, b in zip(s0, s1)], dtype=np.float64)
+    walker_tail = float(wt.max() / max(wt.mean(), 1.0))
     out = dict(
         ms=ms, launches=steps, launch_ms_avg=float(np.mean(launch_ms)),
         launch_ms_minmax=[float(np.min(launch_ms)), float(np.max(launch_ms))],
         steps=nsteps, steps_per_s=nsteps / (ms / 1e3),
         accept=d("accepted") / max(1, nsteps), iters_per_step=d("iters") / max(1, nsteps),
         inner_per_step=d("inner_solves") / max(1, nsteps), passes_per_step=d("refine_passes") / max(1, nsteps),
-        reorders=d("reorders"), refactors=d("refactors"), nonconverged=d("nonconverged"),
+        reorders=d("reorders"), refactors=d("refactors"), ilu_retries=d("ilu_retries"),
+        nonconverged=d("nonconverged"), walker_time_max_over_mean=walker_tail,
         max_N=max(b["max_N"] for b in s1), nnz_per_row=(nnz / n).tolist(),
         phase_us_per_walker_step={k: round(v, 2) for k, v in phase_us.items()},
         alg_bytes=bytes_, alg_bytes_per_launch=bytes_ / steps, autotune=tune,

@@ -105,11 +105,16 @@ typedef struct vmc_params {
                                per walker. */
   int32_t ilu_work_cap;     /* ILUTP work-row capacity (entries of one row during its
                                elimination, candidates, multipliers before the fill
-                               limit); <= 0: 512 entries, 192 candidates, 160 multipliers.
-                               Larger values fit matrices with more fill (e.g. the paper's
-                               b.c.c. k = 1 orbitals at droptol 0.01 need about 9 K^2);
-                               fewer rows are then factored concurrently so the LDS fits.
-                               At most 8192.  Rows beyond it give VMC_ECAPACITY. */
+                               limit); <= 0: 512 entries, 192 candidates, 160 multipliers,
+                               four rows in flight, used where the factorisation's usual
+                               tables (eight rows in flight, 256 entries, 128 candidates,
+                               96 multipliers) overflow: from the first unfinished row, for
+                               64 rows, after which the usual tables resume (the factors
+                               are the same either way).  Larger values fit
+                               matrices with more fill (e.g. the paper's b.c.c. k = 1
+                               orbitals at droptol 0.01 need about 9 K^2) and are used
+                               alone; fewer rows are then factored concurrently so the LDS
+                               fits.  At most 8192.  Rows beyond it give VMC_ECAPACITY. */
   int32_t ilu_drop_norm;    /* ILUTP drop scale of row i: 0 = droptol * ||a_i||_2; 1 =
                                droptol * ||a_i||_1 / nnz(a_i), the mean magnitude that
                                SPARSKIT's ILUTP (the paper's preconditioner, Section 4) uses */
@@ -134,6 +139,10 @@ typedef struct vmc_params {
                                       GMRES iteration, so it misses its tolerance and the
                                       not-converged reorder trigger fires; the solve after the
                                       reorder runs normally */
+#define VMC_TEST_ILU_FAST_SMALL 4  /* the ILUTP's usual tables shrink to 64 entries, so rows
+                                      that hold more during their elimination overflow them and
+                                      the factorisation falls back to the larger tables again
+                                      and again (vmc_stats.ilu_retries counts the fallbacks) */
 
 /* One walker: its physical system (orbital centres and shapes) and start. */
 typedef struct vmc_walker_init {
@@ -212,7 +221,8 @@ typedef struct vmc_stats {
                                applications (sum over solves of m * n * iterations) */
   double refactor_cost;     /* the walker's current cost-balance threshold (<= 0: off) */
   int32_t status;           /* VMC_OK or the first error the walker hit */
-  int32_t pad;
+  int32_t ilu_retries;      /* ILUTP fallbacks: windows of rows that overflowed the usual
+                               tables and were factored with the larger ones */
 } vmc_stats;
 
 /* What vmc_autotune measured or loaded. */

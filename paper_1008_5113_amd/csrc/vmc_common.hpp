@@ -19,30 +19,42 @@ struct LdsLayout {
 
 __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// ILUTP: up to ILU_R rows are factored concurrently, one wave each, every
-// wave with a hashed sparse work row, a candidate table and its multipliers.
-// The capacities are runtime values (DevParams::ilu_*); the defaults suit
-// matrices whose rows stay within a few hundred entries during elimination.
+// ILUTP: rows are factored concurrently, one wave each, every wave with a
+// hashed sparse work row, a candidate table and its multipliers.  The
+// capacities are runtime values (DevParams::ilu, ilu_fast).  The full
+// configuration (ILU_R rows, the ILU_DEF_* tables) suits matrices whose rows
+// stay within a few hundred entries during elimination; the fast one keeps
+// twice the rows in flight in about the same LDS with tables that hold the
+// rows of the usual workloads, and hands the rows around one that overflows
+// them to the full one.
 constexpr int ILU_R = 4;
 constexpr int ILU_DEF_HS = 1024;  // hash slots per wave (power of two)
 constexpr int ILU_DEF_NZ = 512;   // work-row entries per wave
 constexpr int ILU_DEF_C = 192;    // elimination candidates per row
 constexpr int ILU_DEF_L = 160;    // multipliers per row before the fill limit
+constexpr int ILU_FAST_R = 8;
+constexpr int ILU_FAST_HS = 512;
+constexpr int ILU_FAST_NZ = 256;
+constexpr int ILU_FAST_C = 128;
+constexpr int ILU_FAST_L = 96;
+constexpr int ILU_FALLBACK_ROWS = 64;  // rows the full configuration takes after an overflow
 
 __host__ __device__ inline size_t ilu_wave_bytes(int hs, int nz, int c, int l) {
   return align_up((size_t)hs * 4, 16) + align_up((size_t)nz * 2, 16) + (size_t)nz * 8 +
          align_up((size_t)c * 2, 16) * 3 + (size_t)c * 8 + align_up((size_t)l * 2, 16) + (size_t)l * 8;
 }
 
-__host__ __device__ inline size_t ilu_wave_bytes(const DevParams& P) {
-  return ilu_wave_bytes(P.ilu_hs, P.ilu_nz, P.ilu_c, P.ilu_l);
+__host__ __device__ inline size_t ilu_wave_bytes(const IluCfg& C) {
+  return ilu_wave_bytes(C.hs, C.nz, C.c, C.l);
 }
 
 __host__ __device__ inline size_t ilutp_lds_bytes(int n, const DevParams& P) {
   size_t b = 0;
   b += align_up((size_t)n * 2, 16);  // pinv
   b += align_up((size_t)n * 2, 16);  // q
-  const size_t waves = (size_t)P.ilu_r * ilu_wave_bytes(P);
+  const size_t full = (size_t)P.ilu.r * ilu_wave_bytes(P.ilu);
+  const size_t fast = (size_t)P.ilu_fast.r * ilu_wave_bytes(P.ilu_fast);
+  const size_t waves = full > fast ? full : fast;
   const size_t tmp = (size_t)n * 4;  // column relabelling after the factorisation
   b += waves > tmp ? waves : tmp;
   return b;
@@ -100,6 +112,7 @@ struct Smem {
   int* ic;
   void* stmp;
   unsigned long long* ph;
+  unsigned long long* ilu_retries;  // the walker's counter of ILUTP second attempts (or null)
 };
 
 __device__ inline Smem make_smem(char* base, const LdsLayout& L) {
@@ -119,6 +132,7 @@ __device__ inline Smem make_smem(char* base, const LdsLayout& L) {
   s.ic = (int*)(base + L.ic);
   s.stmp = (void*)(base + L.stmp);
   s.ph = nullptr;
+  s.ilu_retries = nullptr;
   return s;
 }
 

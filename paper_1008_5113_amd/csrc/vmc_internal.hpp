@@ -48,6 +48,13 @@ constexpr int WST_NOCONV = 4;
 constexpr int CERR_NOPENDING = 1;   // accept without a pending ratio
 constexpr int CERR_ZERO_RATIO = 2;  // forced acceptance of a zero or non-finite ratio
 
+// One ILUTP configuration: r rows factored concurrently (one wave each), each
+// wave with hs hash slots, a work row of nz entries, c candidates and l
+// multipliers; hshift = 32 - log2(hs).
+struct IluCfg {
+  int r, hs, hshift, nz, c, l;
+};
+
 struct DevParams {
   int precision;
   int maxit;
@@ -61,8 +68,10 @@ struct DevParams {
   int refine_maxit;
   double step;
   int force_reorder_every;
-  // ILUTP per-wave work capacities and concurrent rows (see ilu_default_caps)
-  int ilu_hs, ilu_hshift, ilu_nz, ilu_c, ilu_l, ilu_r;
+  // ILUTP configurations: a factorisation runs with ilu_fast (more rows in
+  // flight, smaller tables; r = 0: none) and is redone with ilu when a row
+  // overflows those tables.  Both give the same factors.
+  IluCfg ilu, ilu_fast;
   int ilu_drop_norm;          // 0: tau = droptol*||a_i||_2; 1: droptol*||a_i||_1/nnz(a_i)
   int test_knobs;             // VMC_TEST_* bits
   int plain_stop;             // ratio solves stop at their tolerance (no ratio-relative target)
@@ -182,6 +191,7 @@ struct WalkerState {
   double refactor_cost;
   double st_upd_entries;
   unsigned long long ph[PH_COUNT];
+  unsigned long long ilu_retries;  // ILUTP fallbacks to the full configuration
 };
 
 }  // namespace vmc

@@ -178,6 +178,9 @@ VMC_PHASE int ilutp_row_cap_extra(const Walker& W, const DevParams& P, Smem& S) 
 constexpr int CAND_DONE = 32767;
 constexpr int IC_FIN = 24;
 constexpr int IC_FAIL = 25;
+// Row-loop status only: a work table of the configuration overflowed (or the
+// wave stopped waiting because another one failed).  It never leaves wg_ilutp.
+constexpr int WST_ILU_TABLE = 8;
 constexpr int SPIN_CAP = 1 << 22;  // bound on every wait; exceeding it is an error
 
 __device__ inline int lds_acquire(const int* p) {
@@ -201,19 +204,19 @@ struct IluWave {
   int hmask, hshift;
 };
 
-__device__ inline IluWave ilu_wave_carve(char* base, const DevParams& P) {
+__device__ inline IluWave ilu_wave_carve(char* base, const IluCfg& C) {
   IluWave R;
-  R.hent = (int*)base;     base += align_up((size_t)P.ilu_hs * 4, 16);
-  R.slab = (short*)base;   base += align_up((size_t)P.ilu_nz * 2, 16);
-  R.sval = (double*)base;  base += (size_t)P.ilu_nz * 8;
-  R.cpos = (short*)base;   base += align_up((size_t)P.ilu_c * 2, 16);
-  R.clab = (short*)base;   base += align_up((size_t)P.ilu_c * 2, 16);
-  R.clen = (short*)base;   base += align_up((size_t)P.ilu_c * 2, 16);
-  R.cdiag = (double*)base; base += (size_t)P.ilu_c * 8;
-  R.lk = (short*)base;     base += align_up((size_t)P.ilu_l * 2, 16);
+  R.hent = (int*)base;     base += align_up((size_t)C.hs * 4, 16);
+  R.slab = (short*)base;   base += align_up((size_t)C.nz * 2, 16);
+  R.sval = (double*)base;  base += (size_t)C.nz * 8;
+  R.cpos = (short*)base;   base += align_up((size_t)C.c * 2, 16);
+  R.clab = (short*)base;   base += align_up((size_t)C.c * 2, 16);
+  R.clen = (short*)base;   base += align_up((size_t)C.c * 2, 16);
+  R.cdiag = (double*)base; base += (size_t)C.c * 8;
+  R.lk = (short*)base;     base += align_up((size_t)C.l * 2, 16);
   R.lv = (double*)base;
-  R.hmask = P.ilu_hs - 1;
-  R.hshift = P.ilu_hshift;
+  R.hmask = C.hs - 1;
+  R.hshift = C.hshift;
   return R;
 }
 
@@ -286,25 +289,27 @@ __device__ inline int ilu_add_cands(const Walker& W, IluWave& R, int ncand, bool
   return ncand + __popcll(mask);
 }
 
-VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
+// The row loop with configuration C over rows [start, end): the factors of
+// those rows into L/U (label space), their pivots into q/pinv (which start as
+// the identity when start is 0).  Rows finish in order; afterwards S.ic[IC_FIN]
+// is the first row not finished.  Returns the OR of the rows' WST_* bits.
+VMC_PHASE int ilu_rows(const Walker& W, const DevParams& P, Smem& S, const IluCfg& C, int pfill, short* pinv,
+                       short* q, char* base, int start, int end) {
   const int n = W.n;
   const int F = W.F;
-  const int pfill = ilutp_row_cap_extra(W, P, S);
-  char* base = S.A;
-  short* pinv = (short*)base;               base += align_up((size_t)n * 2, 16);
-  short* q = (short*)base;                  base += align_up((size_t)n * 2, 16);
   const int wid = wave_id();
-  const int nrow = P.ilu_r, cap_nz = P.ilu_nz, cap_c = P.ilu_c, cap_l = P.ilu_l;
-  IluWave R = ilu_wave_carve(base + (size_t)(wid < nrow ? wid : 0) * ilu_wave_bytes(P), P);
+  const int nrow = C.r, cap_nz = C.nz, cap_c = C.c, cap_l = C.l;
+  IluWave R = ilu_wave_carve(base + (size_t)(wid < nrow ? wid : 0) * ilu_wave_bytes(C), C);
 
-  for (int k = vmc_tid(); k < n; k += NT) {
-    pinv[k] = (short)k;
-    q[k] = (short)k;
-  }
+  if (start == 0)
+    for (int k = vmc_tid(); k < n; k += NT) {
+      pinv[k] = (short)k;
+      q[k] = (short)k;
+    }
   if (wid < nrow)
     for (int h = lane_id(); h <= R.hmask; h += 64) R.hent[h] = -1;
   if (vmc_tid() == 0) {
-    S.ic[IC_FIN] = 0;
+    S.ic[IC_FIN] = start;
     S.ic[IC_FAIL] = 0;
   }
   __syncthreads();
@@ -314,13 +319,13 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
     const double droptol = P.droptol, permtol = P.permtol;
     const bool mean_scale = P.ilu_drop_norm == 1;
     int status = WST_OK;
-    for (int i = wid; i < n; i += nrow) {
+    for (int i = start + wid; i < end; i += nrow) {
       if (lds_acquire(&S.ic[IC_FAIL])) break;
       int known = min(lds_acquire(&S.ic[IC_FIN]), i);  // positions < known are final
       // 1. load row i into the work row; entries at final positions left of
       //    the diagonal are the first candidates
       const int len = W.a_len[i];
-      if (len > cap_nz) { status = WST_CAPACITY; break; }
+      if (len > cap_nz) { status = WST_ILU_TABLE; break; }
       double nrm = 0.0;
       int ncand = 0;
       for (int e0 = 0; e0 < len; e0 += 64) {
@@ -339,7 +344,7 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
         }
         ncand = ilu_add_cands(W, R, ncand, cand, k, c, cap_c);
       }
-      if (ncand > cap_c) { status = WST_CAPACITY; break; }
+      if (ncand > cap_c) { status = WST_ILU_TABLE; break; }
       nrm = wave_sum(nrm);
       // drop scale: the row's 2-norm, or its mean magnitude (SPARSKIT's ILUTP)
       const double tau = droptol * (mean_scale ? nrm / (double)len : sqrt(nrm));
@@ -360,7 +365,7 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
           while (true) {
             f = lds_acquire(&S.ic[IC_FIN]);
             if (f > known) break;
-            if (lds_acquire(&S.ic[IC_FAIL]) || ++spins > SPIN_CAP) { status = WST_CAPACITY; break; }
+            if (lds_acquire(&S.ic[IC_FAIL]) || ++spins > SPIN_CAP) { status = WST_ILU_TABLE; break; }
           }
           if (status != WST_OK) break;
           f = min(f, i);
@@ -374,7 +379,7 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
             }
             ncand = ilu_add_cands(W, R, ncand, add, p, c, cap_c);
           }
-          if (ncand > cap_c) { status = WST_CAPACITY; break; }
+          if (ncand > cap_c) { status = WST_ILU_TABLE; break; }
           known = f;
           continue;
         }
@@ -390,7 +395,7 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
         wave_sync();  // the candidate's entries are read before any lane updates the row
         if (lane == 0) R.cpos[bslot] = (short)CAND_DONE;
         if (fabs(lik) < tau) continue;
-        if (lcount >= cap_l) { status = WST_CAPACITY; break; }
+        if (lcount >= cap_l) { status = WST_ILU_TABLE; break; }
         if (lane == 0) { R.lk[lcount] = (short)best; R.lv[lcount] = lik; }
         ++lcount;
         for (int e0 = 0; e0 < ul; e0 += 64) {
@@ -420,7 +425,7 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
           if (nz > cap_nz) break;
           ncand = ilu_add_cands(W, R, ncand, cand, k2, c2, cap_c);
         }
-        if (nz > cap_nz || ncand > cap_c) { status = WST_CAPACITY; break; }
+        if (nz > cap_nz || ncand > cap_c) { status = WST_ILU_TABLE; break; }
       }
       if (status != WST_OK) break;
 
@@ -572,6 +577,40 @@ VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
   __syncthreads();
   const int status = S.ic[IC_FAIL];
   __syncthreads();
+  return status;
+}
+
+VMC_PHASE int wg_ilutp(const Walker& W, const DevParams& P, Smem& S) {
+  const int n = W.n;
+  const int F = W.F;
+  const int pfill = ilutp_row_cap_extra(W, P, S);
+  char* base = S.A;
+  short* pinv = (short*)base;               base += align_up((size_t)n * 2, 16);
+  short* q = (short*)base;                  base += align_up((size_t)n * 2, 16);
+  // The fast configuration runs until a row overflows its tables.  Rows finish
+  // in order and a row changes q/pinv, L or U only when it finishes, so the
+  // rows before the first unfinished one are final: the full configuration
+  // takes over there for ILU_FALLBACK_ROWS rows (a window that holds every row
+  // that was in flight), then the fast one resumes.  The arithmetic of every
+  // row is the same in both, so the factors are too.
+  int status = WST_OK;
+  if (P.ilu_fast.r > 0) {
+    int start = 0;
+    while (true) {
+      status = ilu_rows(W, P, S, P.ilu_fast, pfill, pinv, q, base, start, n);
+      if (status != WST_ILU_TABLE) break;
+      const int fin = S.ic[IC_FIN];
+      __syncthreads();
+      if (S.ilu_retries && vmc_tid() == 0) *S.ilu_retries += 1;
+      const int stop = min(n, fin + ILU_FALLBACK_ROWS);
+      status = ilu_rows(W, P, S, P.ilu, pfill, pinv, q, base, fin, stop);
+      if (status != WST_OK || stop == n) break;
+      start = stop;
+    }
+  } else {
+    status = ilu_rows(W, P, S, P.ilu, pfill, pinv, q, base, 0, n);
+  }
+  if (status & WST_ILU_TABLE) status = (status & ~WST_ILU_TABLE) | WST_CAPACITY;
   if (status != WST_OK) return status;
 
   // Fold Q into the column numbering: label c -> position pinv[c].

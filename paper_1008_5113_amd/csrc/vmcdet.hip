@@ -41,6 +41,7 @@ __global__ void __launch_bounds__(NT) k_setup(const Walker* __restrict__ walkers
   const Walker& W = walkers[w];
   Smem S = setup_smem(smem, W, P, PREC == VMC_PREC_FP64 ? 8 : 4);
   S.ph = states[w].ph;
+  S.ilu_retries = &states[w].ilu_retries;
   if (threadIdx.x < 32) S.ic[threadIdx.x] = 0;
   __syncthreads();
   int st = WST_OK;
@@ -81,6 +82,7 @@ __global__ void __launch_bounds__(NT, 4) k_ratio(const Walker* __restrict__ walk
   WalkerState* ws = states + w;
   Smem S = setup_smem(smem, W, P, PREC == VMC_PREC_FP64 ? 8 : 4);
   S.ph = states[w].ph;
+  S.ilu_retries = &states[w].ilu_retries;
   if (threadIdx.x < 32) S.ic[threadIdx.x] = 0;
   __syncthreads();
   if (ws->status != WST_OK) {
@@ -128,6 +130,7 @@ __global__ void __launch_bounds__(NT) k_accept(const Walker* __restrict__ walker
   WalkerState* ws = states + w;
   Smem S = setup_smem(smem, W, P, PREC == VMC_PREC_FP64 ? 8 : 4);
   S.ph = states[w].ph;
+  S.ilu_retries = &states[w].ilu_retries;
   if (threadIdx.x < 32) S.ic[threadIdx.x] = 0;
   __syncthreads();
   int err = 0;
@@ -163,6 +166,7 @@ __global__ void __launch_bounds__(NT, 4) k_run(const Walker* __restrict__ walker
   WalkerState* ws = states + w;
   Smem S = setup_smem(smem, W, P, PREC == VMC_PREC_FP64 ? 8 : 4);
   S.ph = states[w].ph;
+  S.ilu_retries = &states[w].ilu_retries;
   if (threadIdx.x < 32) S.ic[threadIdx.x] = 0;
   __syncthreads();
   PhaseClock pstep;
@@ -200,6 +204,7 @@ __global__ void __launch_bounds__(NT, 4) k_energy(const Walker* __restrict__ wal
   WalkerState* ws = states + w;
   Smem S = setup_smem(smem, W, P, PREC == VMC_PREC_FP64 ? 8 : 4);
   S.ph = states[w].ph;
+  S.ilu_retries = &states[w].ilu_retries;
   if (threadIdx.x < 32) S.ic[threadIdx.x] = 0;
   __syncthreads();
   if (ws->status != WST_OK || ws->pend_valid) {
@@ -659,11 +664,13 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
   d.ilu_drop_norm = p->ilu_drop_norm;
   d.test_knobs = p->test_knobs;
   d.plain_stop = p->plain_stop != 0;
-  d.ilu_r = ILU_R;
-  d.ilu_hs = ILU_DEF_HS;
-  d.ilu_nz = ILU_DEF_NZ;
-  d.ilu_c = ILU_DEF_C;
-  d.ilu_l = ILU_DEF_L;
+  auto hshift_of = [](int hs) {
+    int lg = 0;
+    while ((1 << lg) < hs) ++lg;
+    return 32 - lg;
+  };
+  d.ilu = IluCfg{ILU_R, ILU_DEF_HS, 0, ILU_DEF_NZ, ILU_DEF_C, ILU_DEF_L};
+  d.ilu_fast = IluCfg{ILU_FAST_R, ILU_FAST_HS, 0, ILU_FAST_NZ, ILU_FAST_C, ILU_FAST_L};
   if (p->ilu_work_cap > 0) {
     if (p->ilu_work_cap > 8192) {
       delete c;
@@ -671,17 +678,20 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
       return VMC_EINVAL;
     }
     const int cap = (p->ilu_work_cap + 63) / 64 * 64;
-    d.ilu_nz = std::max(cap, ILU_DEF_NZ);
-    d.ilu_c = std::max(cap, ILU_DEF_C);
-    d.ilu_l = std::max(cap, ILU_DEF_L);
-    d.ilu_hs = ILU_DEF_HS;
-    while (d.ilu_hs < 2 * d.ilu_nz) d.ilu_hs *= 2;
+    d.ilu.nz = std::max(cap, ILU_DEF_NZ);
+    d.ilu.c = std::max(cap, ILU_DEF_C);
+    d.ilu.l = std::max(cap, ILU_DEF_L);
+    d.ilu.hs = ILU_DEF_HS;
+    while (d.ilu.hs < 2 * d.ilu.nz) d.ilu.hs *= 2;
+    d.ilu_fast.r = 0;  // a given capacity is the one used
   }
-  {
-    int lg = 0;
-    while ((1 << lg) < d.ilu_hs) ++lg;
-    d.ilu_hshift = 32 - lg;
+  if (p->test_knobs & VMC_TEST_ILU_FAST_SMALL) {
+    d.ilu_fast.nz = 64;
+    d.ilu_fast.c = 64;
+    d.ilu_fast.l = 16;
   }
+  d.ilu.hshift = hshift_of(d.ilu.hs);
+  d.ilu_fast.hshift = hshift_of(d.ilu_fast.hs);
 
   const int ktb = p->precision == VMC_PREC_FP64 ? 8 : 4;
   auto fail = [&](vmc_status s, const std::string& msg) {
@@ -868,15 +878,32 @@ vmc_status vmc_create(void** ctx_out, const vmc_params* p, int32_t n_walkers, co
   if (hipMemcpy(c->d_all, all.data(), sizeof(int) * n_walkers, hipMemcpyHostToDevice) != hipSuccess)
     return fail(VMC_EHIP, "initial copy failed");
 
-  int dev = 0, maxlds = 0;
+  int dev = 0, maxlds = 0, cu_lds = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  (void)hipDeviceGetAttribute(&cu_lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+  if (cu_lds <= 0) cu_lds = maxlds;
   // as many concurrently factored ILUTP rows as the LDS holds (results do not
-  // depend on it)
+  // depend on it): first the full configuration alone, then the fast one with
+  // as many rows as keep the workgroups per CU that the full one allows
+  const IluCfg fast = c->dp.ilu_fast;
+  c->dp.ilu_fast.r = 0;
   LdsLayout L = lds_layout(c->maxn, ktb, c->dp);
-  while (c->dp.ilu_r > 1 && maxlds > 0 && (int)L.total > maxlds) {
-    c->dp.ilu_r -= 1;
+  while (c->dp.ilu.r > 1 && maxlds > 0 && (int)L.total > maxlds) {
+    c->dp.ilu.r -= 1;
     L = lds_layout(c->maxn, ktb, c->dp);
+  }
+  const auto per_cu = [&](size_t bytes) { return cu_lds > 0 ? (size_t)cu_lds / bytes : 1; };
+  for (int r = fast.r; r > c->dp.ilu.r; --r) {
+    DevParams t = c->dp;
+    t.ilu_fast = fast;
+    t.ilu_fast.r = r;
+    const LdsLayout Lf = lds_layout(c->maxn, ktb, t);
+    if ((maxlds <= 0 || (int)Lf.total <= maxlds) && per_cu(Lf.total) >= per_cu(L.total)) {
+      c->dp.ilu_fast = t.ilu_fast;
+      L = Lf;
+      break;
+    }
   }
   c->lds = L.total;
   if (maxlds > 0 && (int)c->lds > maxlds) {
@@ -1555,6 +1582,7 @@ vmc_status vmc_get_stats(void* ctx, vmc_stats* out) {
     o.sum_N = s.st_sumN;
     o.update_entries = s.st_upd_entries;
     o.refactor_cost = s.refactor_cost;
+    o.ilu_retries = (int32_t)s.ilu_retries;
     o.status = (s.status & WST_CAPACITY)   ? VMC_ECAPACITY
                : (s.status & WST_SINGULAR) ? VMC_ESINGULAR
                : (s.status & WST_NOCONV)   ? VMC_ENOCONV

@@ -42,6 +42,7 @@ FLAG_NOCONV = 1024
 
 TEST_ZERO_RATIO = 1
 TEST_FIRST_SOLVE_ONE_ITER = 2
+TEST_ILU_FAST_SMALL = 4
 
 PHASE_NAMES = ["prepare", "lsolve", "usolve", "updates", "spmv", "ortho", "solution", "resid64",
                "accept", "refactor", "reorder", "launch"]
@@ -148,7 +149,7 @@ class VmcStats(ctypes.Structure):
         ("phase_ticks", ctypes.c_int64 * 12),
         ("max_N", ctypes.c_double), ("sum_N", ctypes.c_double),
         ("update_entries", ctypes.c_double), ("refactor_cost", ctypes.c_double),
-        ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("status", ctypes.c_int32), ("ilu_retries", ctypes.c_int32),
     ]
 
 

@@ -21,21 +21,25 @@ int main() {
   const int mms[] = {1, 32, 200, 256};
   const int Ws[] = {16, 96, 176, 256};
   for (int prec = 0; prec < 2; ++prec)
-    for (int n : ns) for (int it : its) for (int mm : mms) for (int ir = 1; ir <= ILU_R; ++ir) {
+    for (int n : ns) for (int it : its) for (int mm : mms) for (int ir = 1; ir <= ILU_R; ++ir)
+    for (int fr : {0, ILU_FAST_R}) {
       DevParams P{};
-      P.maxit = it; P.m_max = mm; P.ilu_r = ir; P.ilu_hs = ILU_DEF_HS; P.ilu_nz = ILU_DEF_NZ;
-      P.ilu_c = ILU_DEF_C; P.ilu_l = ILU_DEF_L;
+      P.maxit = it; P.m_max = mm;
+      P.ilu = IluCfg{ir, ILU_DEF_HS, 22, ILU_DEF_NZ, ILU_DEF_C, ILU_DEF_L};
+      P.ilu_fast = IluCfg{fr, ILU_FAST_HS, 23, ILU_FAST_NZ, ILU_FAST_C, ILU_FAST_L};
       const int ktb = prec ? 4 : 8;
       LdsLayout L = lds_layout(n, ktb, P);
       for (int W : Ws) {
         if (W > n && n > 16) continue;
         const size_t prep = 2 * (align_up((size_t)W * 4, 16) + (size_t)W * 8);
-        printf("%d %d %d %d %d %d %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", prec, n, it, mm, ir, W,
+        printf("%d %d %d %d %d %d %d %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", prec, n, it, mm, ir, fr, W,
                L.hb, L.cs, L.sn, L.gg, L.rp, L.yb, L.ux, L.gb, L.cb, L.red, L.sc, L.ic, L.stmp, L.total);
         (void)prep;
       }
     }
-  printf("DTILE %d NT %d NWAVE %d BLK %d\n", DTILE, NT, NWAVE, BLK);
+  printf("DTILE %d NT %d NWAVE %d BLK %d FULL_WAVE %zu FAST_WAVE %zu\n", DTILE, NT, NWAVE, BLK,
+         ilu_wave_bytes(ILU_DEF_HS, ILU_DEF_NZ, ILU_DEF_C, ILU_DEF_L),
+         ilu_wave_bytes(ILU_FAST_HS, ILU_FAST_NZ, ILU_FAST_C, ILU_FAST_L));
   return 0;
 }
 '''
@@ -63,9 +67,13 @@ def _align(x, a):
 def test_every_phase_fits_its_region(tmp_path):
     rows, C = _layouts(tmp_path)
     NT, NWAVE, DTILE = C["NT"], C["NWAVE"], C["DTILE"]
-    for prec, n, it, mm, ir, W, hb, cs, sn, gg, rp, yb, ux, gb, cb, red, sc, ic, stmp, total in rows:
+    for prec, n, it, mm, ir, fr, W, hb, cs, sn, gg, rp, yb, ux, gb, cb, red, sc, ic, stmp, total in rows:
         ktb = 4 if prec else 8
-        ctx = (prec, n, it, mm, ir, W)
+        ctx = (prec, n, it, mm, ir, fr, W)
+        # the ILUTP phase: pinv and q, then either configuration's wave tables
+        # (or the n ints of the column relabelling)
+        waves = max(ir * C["FULL_WAVE"], fr * C["FAST_WAVE"], 4 * n)
+        assert red >= 2 * _align(2 * n, 16) + waves, ctx
         # solve phase: x, the in-block tile, then the GMRES scalars in order
         assert hb >= _align(n, 4) * ktb + _align(DTILE * ktb, 16), ctx
         assert cs >= hb + (it + 2) * 8 and sn >= cs + (it + 1) * 8 and gg >= sn + (it + 1) * 8, ctx
