@@ -196,7 +196,7 @@ struct IluWave {
   short* slab;    // slot -> label
   double* sval;   // slot -> value
   short* cpos;    // candidate position (CAND_DONE once eliminated)
-  short* clab;    // candidate label
+  short* cslot;   // work-row slot of the candidate's label
   short* clen;    // length of U row cpos
   double* cdiag;  // u_kk of row cpos
   short* lk;      // kept multipliers: positions
@@ -210,7 +210,7 @@ __device__ inline IluWave ilu_wave_carve(char* base, const IluCfg& C) {
   R.slab = (short*)base;   base += align_up((size_t)C.nz * 2, 16);
   R.sval = (double*)base;  base += (size_t)C.nz * 8;
   R.cpos = (short*)base;   base += align_up((size_t)C.c * 2, 16);
-  R.clab = (short*)base;   base += align_up((size_t)C.c * 2, 16);
+  R.cslot = (short*)base;  base += align_up((size_t)C.c * 2, 16);
   R.clen = (short*)base;   base += align_up((size_t)C.c * 2, 16);
   R.cdiag = (double*)base; base += (size_t)C.c * 8;
   R.lk = (short*)base;     base += align_up((size_t)C.l * 2, 16);
@@ -251,7 +251,7 @@ __device__ inline int ilu_compact(IluWave& R, int ncand) {
     double d = 0.0;
     if (s < ncand) {
       p = R.cpos[s];
-      c = R.clab[s];
+      c = R.cslot[s];
       l = R.clen[s];
       d = R.cdiag[s];
     }
@@ -261,7 +261,7 @@ __device__ inline int ilu_compact(IluWave& R, int ncand) {
     if (live) {
       const int t = w + before;
       R.cpos[t] = (short)p;
-      R.clab[t] = (short)c;
+      R.cslot[t] = (short)c;
       R.clen[t] = (short)l;
       R.cdiag[t] = d;
     }
@@ -270,10 +270,10 @@ __device__ inline int ilu_compact(IluWave& R, int ncand) {
   return w;
 }
 
-// Append the lanes flagged `add` as candidates (position p, label c), with
-// the diagonal and length of U row p.  Returns the new count; a count above
-// cap means the table overflowed.
-__device__ inline int ilu_add_cands(const Walker& W, IluWave& R, int ncand, bool add, int p, int c, int cap) {
+// Append the lanes flagged `add` as candidates (position p, its label at
+// work-row slot sl), with the diagonal and length of U row p.  Returns the new
+// count; a count above cap means the table overflowed.
+__device__ inline int ilu_add_cands(const Walker& W, IluWave& R, int ncand, bool add, int p, int sl, int cap) {
   const int lane = lane_id();
   const unsigned long long mask = __ballot(add);
   if (ncand + (int)__popcll(mask) > cap) ncand = ilu_compact(R, ncand);
@@ -281,7 +281,7 @@ __device__ inline int ilu_add_cands(const Walker& W, IluWave& R, int ncand, bool
   if (add && ncand + before < cap) {
     const int s = ncand + before;
     R.cpos[s] = (short)p;
-    R.clab[s] = (short)c;
+    R.cslot[s] = (short)sl;
     R.cdiag[s] = W.u_diag[p];
     R.clen[s] = (short)W.u_len[p];
   }
@@ -342,7 +342,7 @@ VMC_PHASE int ilu_rows(const Walker& W, const DevParams& P, Smem& S, const IluCf
           k = pinv[c];
           cand = k < known;
         }
-        ncand = ilu_add_cands(W, R, ncand, cand, k, c, cap_c);
+        ncand = ilu_add_cands(W, R, ncand, cand, k, e, cap_c);
       }
       if (ncand > cap_c) { status = WST_ILU_TABLE; break; }
       nrm = wave_sum(nrm);
@@ -352,10 +352,16 @@ VMC_PHASE int ilu_rows(const Walker& W, const DevParams& P, Smem& S, const IluCf
       int lcount = 0;
       // 2. eliminate in increasing position order
       while (true) {
-        int best = CAND_DONE, bslot = -1;
+        // each lane keeps the fields of its smallest candidate, so the
+        // winner's come back by readlane instead of further LDS round trips
+        int best = CAND_DONE, bslot = -1, bsk = 0, bul = 0;
+        double bdiag = 1.0;
         for (int s = lane; s < ncand; s += 64) {
           const int p = R.cpos[s];
-          if (p < best) { best = p; bslot = s; }
+          const int sl = R.cslot[s];
+          const int cl = R.clen[s];
+          const double dg = R.cdiag[s];
+          if (p < best) { best = p; bslot = s; bsk = sl; bul = cl; bdiag = dg; }
         }
         const int bmin = wave_mini(best);
         if (bmin == CAND_DONE) {
@@ -372,12 +378,12 @@ VMC_PHASE int ilu_rows(const Walker& W, const DevParams& P, Smem& S, const IluCf
           for (int p0 = known; p0 < f; p0 += 64) {
             const int p = p0 + lane;
             bool add = false;
-            int c = 0;
+            int sl = 0;
             if (p < f) {
-              c = q[p];
-              add = ilu_find(R, c) >= 0;
+              sl = ilu_find(R, q[p]);
+              add = sl >= 0;
             }
-            ncand = ilu_add_cands(W, R, ncand, add, p, c, cap_c);
+            ncand = ilu_add_cands(W, R, ncand, add, p, sl, cap_c);
           }
           if (ncand > cap_c) { status = WST_ILU_TABLE; break; }
           known = f;
@@ -386,12 +392,16 @@ VMC_PHASE int ilu_rows(const Walker& W, const DevParams& P, Smem& S, const IluCf
         {
           // positions are distinct, so exactly one lane holds the minimum
           const unsigned long long who = __ballot(best == bmin);
-          bslot = readlane_i(bslot, __ffsll((long long)who) - 1);
+          const int wl = __ffsll((long long)who) - 1;
+          bslot = readlane_i(bslot, wl);
+          bsk = readlane_i(bsk, wl);
+          bul = readlane_i(bul, wl);
+          bdiag = readlane_t(bdiag, wl);
           best = bmin;
         }
-        const int sk = ilu_find(R, R.clab[bslot]);
-        const double lik = R.sval[sk] / R.cdiag[bslot];
-        const int ul = R.clen[bslot];
+        const int sk = bsk;
+        const double lik = R.sval[sk] / bdiag;
+        const int ul = bul;
         wave_sync();  // the candidate's entries are read before any lane updates the row
         if (lane == 0) R.cpos[bslot] = (short)CAND_DONE;
         if (fabs(lik) < tau) continue;
@@ -413,8 +423,9 @@ VMC_PHASE int ilu_rows(const Walker& W, const DevParams& P, Smem& S, const IluCf
           }
           const unsigned long long mask = __ballot(isnew);
           const int before = __popcll(mask & ((1ull << lane) - 1ull));
+          int s2 = 0;
           if (isnew && nz + before < cap_nz) {
-            const int s2 = nz + before;
+            s2 = nz + before;
             R.slab[s2] = (short)c2;
             R.sval[s2] = -lik * v2;
             ilu_insert(R, c2, s2);
@@ -423,7 +434,7 @@ VMC_PHASE int ilu_rows(const Walker& W, const DevParams& P, Smem& S, const IluCf
           }
           nz += __popcll(mask);
           if (nz > cap_nz) break;
-          ncand = ilu_add_cands(W, R, ncand, cand, k2, c2, cap_c);
+          ncand = ilu_add_cands(W, R, ncand, cand, k2, s2, cap_c);
         }
         if (nz > cap_nz || ncand > cap_c) { status = WST_ILU_TABLE; break; }
       }
