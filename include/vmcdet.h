@@ -114,7 +114,10 @@ typedef struct vmc_params {
                                matrices with more fill (e.g. the paper's b.c.c. k = 1
                                orbitals at droptol 0.01 need about 9 K^2) and are used
                                alone; fewer rows are then factored concurrently so the LDS
-                               fits.  At most 8192.  Rows beyond it give VMC_ECAPACITY. */
+                               fits.  At most 8192.  The multiplier table keeps the
+                               largest multipliers once full, which loses none of the
+                               nL0 + p a row stores while that many fit.  Rows beyond
+                               these capacities give VMC_ECAPACITY. */
   int32_t ilu_drop_norm;    /* ILUTP drop scale of row i: 0 = droptol * ||a_i||_2; 1 =
                                droptol * ||a_i||_1 / nnz(a_i), the mean magnitude that
                                SPARSKIT's ILUTP (the paper's preconditioner, Section 4) uses */

@@ -350,6 +350,7 @@ VMC_PHASE int ilu_rows(const Walker& W, const DevParams& P, Smem& S, const IluCf
       const double tau = droptol * (mean_scale ? nrm / (double)len : sqrt(nrm));
       int nz = len;
       int lcount = 0;
+      bool lfull = false;  // multipliers were kept beyond the table
       // 2. eliminate in increasing position order
       while (true) {
         // each lane keeps the fields of its smallest candidate, so the
@@ -405,9 +406,37 @@ VMC_PHASE int ilu_rows(const Walker& W, const DevParams& P, Smem& S, const IluCf
         wave_sync();  // the candidate's entries are read before any lane updates the row
         if (lane == 0) R.cpos[bslot] = (short)CAND_DONE;
         if (fabs(lik) < tau) continue;
-        if (lcount >= cap_l) { status = WST_ILU_TABLE; break; }
-        if (lane == 0) { R.lk[lcount] = (short)best; R.lv[lcount] = lik; }
-        ++lcount;
+        if (lcount < cap_l) {
+          if (lane == 0) { R.lk[lcount] = (short)best; R.lv[lcount] = lik; }
+          ++lcount;
+        } else {
+          // A full table keeps the cap_l multipliers that rank first (larger
+          // magnitude, then smaller position).  The row stores only its
+          // nL0 + p first, so none of those is lost while cap_l >= nL0 + p,
+          // which the L part checks.  The new multiplier replaces the table's
+          // last-ranked one if it ranks before it.
+          double wa = 1e308;
+          int wp = -1, wi = -1;
+          for (int f = lane; f < cap_l; f += 64) {
+            const double a3 = fabs(R.lv[f]);
+            const int p3 = R.lk[f];
+            if (a3 < wa || (a3 == wa && p3 > wp)) { wa = a3; wp = p3; wi = f; }
+          }
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) {
+            const double oa = __shfl_xor(wa, o, 64);
+            const int op = __shfl_xor(wp, o, 64);
+            const int oi = __shfl_xor(wi, o, 64);
+            if (oa < wa || (oa == wa && op > wp)) { wa = oa; wp = op; wi = oi; }
+          }
+          const double al = fabs(lik);
+          wave_sync();  // every lane has read the table before lane 0 replaces an entry
+          if (lane == 0 && (al > wa || (al == wa && best < wp))) {
+            R.lk[wi] = (short)best;
+            R.lv[wi] = lik;
+          }
+          lfull = true;
+        }
         for (int e0 = 0; e0 < ul; e0 += 64) {
           const int e = e0 + lane;
           bool isnew = false, cand = false;
@@ -545,6 +574,7 @@ VMC_PHASE int ilu_rows(const Walker& W, const DevParams& P, Smem& S, const IluCf
       }
       if (dval == 0.0) { status = WST_SINGULAR; break; }
       // 5. L part: keep the lcap largest multipliers
+      if (lfull && lcap > cap_l) { status = WST_ILU_TABLE; break; }
       int lwrite = 0;
       int* lcol = W.l_col + (size_t)i * F;
       double* lval = W.l_val + (size_t)i * F;
