@@ -639,7 +639,7 @@ def main(argv=None):
                    "refactor": (f"cost balance, autotuned over one trial launch of {args.block} steps, "
                                 f"cap {args.m_max}" if args.autotune
                                 else f"every {args.m_max or inst.params.m_max} updates"),
-                   "lattice": ",".join("x".join(str(x) for x in s.lattice) for s in inst.systems),
+                   "lattice": ",".join(dict.fromkeys("x".join(str(x) for x in s.lattice) for s in inst.systems)),
                    "path": headpath},
         "paths": results,
     }
