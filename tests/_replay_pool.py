@@ -19,14 +19,35 @@ def _replay_one(args):
         return walker, rep
 
 
-def replay_walkers(workload, step, starts, logs, procs, mode="sm"):
+def replay_walkers(workload, step, starts, logs, procs, mode="sm", parts=1):
     """Replay walker w's log from positions starts[w] (dict walker -> array) in
-    `procs` processes; returns {walker: ReplayReport}."""
+    `procs` processes; returns {walker: ReplayReport}.  With parts > 1 each log
+    is cut into that many consecutive pieces, each replayed from the positions
+    the log itself gives at its start (a fresh inverse per piece), and the
+    pieces' reports are merged in order."""
+    from oracle.chain import ReplayReport, StepRecord, positions_after
     jobs = []
     for w, log in logs.items():
         recs = [(int(r["step"]), int(r["particle"]), tuple(r["new_pos"]), float(r["ratio"]),
                  float(r["u_acc"]), bool(r["flags"] & 1)) for r in log]
-        jobs.append((workload, w, starts[w], step, recs, mode))
+        cut = [len(recs) * k // parts for k in range(parts + 1)]
+        pos = np.array(starts[w], dtype=np.float64)
+        for k in range(parts):
+            piece = recs[cut[k]:cut[k + 1]]
+            jobs.append((workload, w, pos.copy(), step, piece, mode))
+            pos = positions_after(pos, [StepRecord(*r) for r in piece])
     ctx = mp.get_context("spawn")
     with ctx.Pool(min(procs, len(jobs))) as pool:
-        return dict(pool.map(_replay_one, jobs))
+        done = pool.map(_replay_one, jobs)
+    out = {}
+    for w, rep in done:  # pool.map keeps the job order: pieces in order
+        m = out.setdefault(w, ReplayReport())
+        m.steps += rep.steps
+        m.max_dlog = max(m.max_dlog, rep.max_dlog)
+        m.dlogs += rep.dlogs
+        m.pos_mismatch += rep.pos_mismatch
+        m.sign_mismatch += rep.sign_mismatch
+        m.decision_mismatch += rep.decision_mismatch
+        m.decision_mismatch_outside_tol += rep.decision_mismatch_outside_tol
+        m.oracle_ratios += rep.oracle_ratios
+    return out
