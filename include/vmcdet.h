@@ -367,6 +367,22 @@ vmc_status vmc_run_steps_energy(void* ctx, int32_t steps, vmc_step_record* dev_l
    vmc_sm_get_inverse copies walker w's inverse to host_out (n*n doubles,
    host_out[p*n + j] = (A^{-1})_{jp}, particle p, site j).  Synchronous. */
 vmc_status vmc_sm_prepare(void* ctx, double tol);
+/* vmc_sm_prepare for callers that cannot allocate device memory (code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+   the same inverses, computed by the same kernels, but stored in a static
+   device array of 64 MiB that the library holds on each GPU it runs on until
+   the process ends, instead of buffers the context allocates.  It calls no
+   hipMalloc, hipFree or other allocating routine (an error message may
+   allocate host memory).  The inverses, their pointer table and the
+   not-converged flags must fit 64 MiB: sum over walkers of
+   ceil8(n) * n * 8 bytes, each rounded up to 256, plus 256-byte-rounded
+   8 * walkers and 4 * walkers; larger requests return VMC_EINVAL and leave
+   the context as it was.  One array per GPU: the last context to call this
+   on a GPU owns it, and the contexts that held it before get VMC_ESTATE from
+   vmc_sm_run_steps and vmc_sm_get_inverse until they prepare again.  Calls
+   on one GPU that overlap race.  vmc_sm_prepare afterwards goes back to the
+   context's own buffers.  Synchronous. */
+vmc_status vmc_sm_prepare_static(void* ctx, double tol);
 vmc_status vmc_sm_run_steps(void* ctx, int32_t steps, vmc_step_record* dev_log, int64_t log_cap);
 vmc_status vmc_sm_get_inverse(void* ctx, int32_t walker, double* host_out);
 

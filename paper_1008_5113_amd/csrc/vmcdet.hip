@@ -490,8 +490,12 @@ struct Ctx {
   bool g_order = false;
   // standard algorithm: one stored inverse per walker, and the device table of them
   std::vector<void*> sm_bufs;
-  double** d_smB = nullptr;
+  double** d_smB = nullptr;        // the inverse table and flags in use
   int* d_nonconv = nullptr;
+  double** smB_own = nullptr;      // the ones vmc_sm_prepare allocated
+  int* nonconv_own = nullptr;
+  bool sm_static = false;          // the inverses in use live in the static scratch
+  int sm_dev = -1;                 // the device whose scratch holds them
   int max_cap = 0;
   // the stored inverses belong to the walkers' current matrices: set by
   // vmc_sm_prepare, kept by vmc_sm_run_steps, cleared by every other call that
@@ -557,18 +561,69 @@ vmc_status check_sparse(Ctx* c, const int32_t* walkers, int32_t count) {
 }
 
 vmc_status walker_errors(Ctx* c) {
-  std::vector<WalkerState> hs(c->nw);
-  HIPCHK(c, hipMemcpyAsync(hs.data(), c->dS, sizeof(WalkerState) * c->nw, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  for (int w = 0; w < c->nw; ++w) {
-    if (hs[w].status & WST_CAPACITY) { c->err = "walker " + std::to_string(w) + ": capacity exceeded"; return VMC_ECAPACITY; }
-    if (hs[w].status & WST_SINGULAR) { c->err = "walker " + std::to_string(w) + ": singular pivot"; return VMC_ESINGULAR; }
-    if (hs[w].status & WST_NOCONV) {
-      c->err = "walker " + std::to_string(w) + ": GMRES did not converge even after reorder and refactor";
-      return VMC_ENOCONV;
+  // the walker states come back a few at a time through a stack buffer, so
+  // the check allocates nothing
+  constexpr int CH = 8;
+  WalkerState hs[CH];
+  for (int w0 = 0; w0 < c->nw; w0 += CH) {
+    const int cnt = std::min(CH, c->nw - w0);
+    HIPCHK(c, hipMemcpyAsync(hs, c->dS + w0, sizeof(WalkerState) * cnt, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < cnt; ++k) {
+      const int w = w0 + k;
+      if (hs[k].status & WST_CAPACITY) { c->err = "walker " + std::to_string(w) + ": capacity exceeded"; return VMC_ECAPACITY; }
+      if (hs[k].status & WST_SINGULAR) { c->err = "walker " + std::to_string(w) + ": singular pivot"; return VMC_ESINGULAR; }
+      if (hs[k].status & WST_NOCONV) {
+        c->err = "walker " + std::to_string(w) + ": GMRES did not converge even after reorder and refactor";
+        return VMC_ENOCONV;
+      }
     }
   }
   return VMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch of vmc_sm_prepare_static: one array per GPU the library runs
+// on, held until the process ends.  A call lays out in it the inverse table
+// (one pointer per walker), the not-converged flags and then every walker's
+// inverse (sm_ld(n) x n doubles), each part 256-byte aligned.  Host code uses
+// the device address hipGetSymbolAddress gives for the current device, never
+// the array's name.  The last context to fill a GPU's scratch owns it.
+constexpr size_t SM_STATIC_BYTES = (size_t)64 << 20;
+constexpr int SM_STATIC_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[SM_STATIC_BYTES];
+static char* g_scratch_ptr[SM_STATIC_DEVICES];
+static const Ctx* g_scratch_owner[SM_STATIC_DEVICES];
+
+size_t sm_static_offset(const Ctx* c, int walker) {
+  size_t o = align_up((size_t)c->nw * sizeof(double*), 256) + align_up((size_t)c->nw * 4, 256);
+  for (int w = 0; w < walker; ++w) o += align_up(sm_ld(c->hw[w].n) * (size_t)c->hw[w].n * 8, 256);
+  return o;
+}
+
+bool sm_static_owned(const Ctx* c) {
+  return c->sm_dev >= 0 && c->sm_dev < SM_STATIC_DEVICES && g_scratch_owner[c->sm_dev] == c;
+}
+
+const void* sm_static_inverse(const Ctx* c, int walker) {
+  if (!sm_static_owned(c)) return nullptr;
+  return g_scratch_ptr[c->sm_dev] + sm_static_offset(c, walker);
+}
+
+void sm_static_release(const Ctx* c) {
+  if (c->sm_static && sm_static_owned(c)) g_scratch_owner[c->sm_dev] = nullptr;
+}
+
+// The inverse table of a static layout (the same offsets as sm_static_offset).
+__global__ void k_sm_table(const Walker* __restrict__ walkers, int nw, char* base) {
+  if (threadIdx.x != 0) return;
+  double** tab = (double**)base;
+  size_t o = align_up((size_t)nw * sizeof(double*), 256) + align_up((size_t)nw * 4, 256);
+  for (int w = 0; w < nw; ++w) {
+    tab[w] = (double*)(base + o);
+    const int n = walkers[w].n;
+    o += align_up(sm_ld(n) * (size_t)n * 8, 256);
+  }
 }
 
 // Caller errors recorded by device-pointer calls since the last check; clears them.
@@ -1278,7 +1333,7 @@ vmc_status vmc_sm_prepare(void* ctx, double tol) {
   Ctx* c = (Ctx*)ctx;
   if (!c || !(tol > 0.0)) return VMC_EINVAL;
   if (vmc_status s = check_sparse(c, nullptr, c->nw)) return s;
-  if (!c->d_smB) {
+  if (!c->smB_own) {
     std::vector<double*> ptrs(c->nw);
     for (int w = 0; w < c->nw; ++w) {
       void* b = nullptr;
@@ -1304,10 +1359,14 @@ vmc_status vmc_sm_prepare(void* ctx, double tol) {
       c->err = "device allocation failed";
       return VMC_ENOMEM;
     }
-    c->d_smB = (double**)tab;
-    c->d_nonconv = (int*)flags;
-    HIPCHK(c, hipMemcpyAsync(c->d_smB, ptrs.data(), sizeof(double*) * c->nw, hipMemcpyHostToDevice, c->stream));
+    c->smB_own = (double**)tab;
+    c->nonconv_own = (int*)flags;
+    HIPCHK(c, hipMemcpyAsync(c->smB_own, ptrs.data(), sizeof(double*) * c->nw, hipMemcpyHostToDevice, c->stream));
   }
+  sm_static_release(c);
+  c->d_smB = c->smB_own;
+  c->d_nonconv = c->nonconv_own;
+  c->sm_static = false;
   c->sm_current = false;
   if (c->dp.precision == VMC_PREC_FP64)
     hipLaunchKernelGGL(k_inverse_cols<VMC_PREC_FP64>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp,
@@ -1331,10 +1390,73 @@ vmc_status vmc_sm_prepare(void* ctx, double tol) {
   return st;
 }
 
+vmc_status vmc_sm_prepare_static(void* ctx, double tol) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || !(tol > 0.0)) return VMC_EINVAL;
+  if (vmc_status s = check_sparse(c, nullptr, c->nw)) return s;
+  int dev = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= SM_STATIC_DEVICES) {
+    c->err = "vmc_sm_prepare_static: device index beyond the static scratch table";
+    return VMC_EINVAL;
+  }
+  const size_t need = sm_static_offset(c, c->nw);
+  if (need > SM_STATIC_BYTES) {
+    c->err = "vmc_sm_prepare_static: the inverses need " + std::to_string(need) + " bytes, the static scratch holds " +
+             std::to_string(SM_STATIC_BYTES);
+    return VMC_EINVAL;
+  }
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(c, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = (char*)ptr;
+  }
+  char* base = g_scratch_ptr[dev];
+  int* flags = (int*)(base + align_up((size_t)c->nw * sizeof(double*), 256));
+  c->sm_current = false;
+  // this context takes the scratch: another one that held it can no longer
+  // run on its inverses (vmc_sm_run_steps and vmc_sm_get_inverse refuse)
+  g_scratch_owner[dev] = c;
+  c->sm_dev = dev;
+  c->sm_static = true;
+  c->d_smB = (double**)base;
+  c->d_nonconv = flags;
+  hipLaunchKernelGGL(k_sm_table, dim3(1), dim3(64), 0, c->stream, c->dW, c->nw, base);
+  HIPCHK(c, hipGetLastError());
+  if (c->dp.precision == VMC_PREC_FP64)
+    hipLaunchKernelGGL(k_inverse_cols<VMC_PREC_FP64>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp,
+                       (double* const*)c->d_smB, 0, c->maxn, tol, c->d_nonconv);
+  else
+    hipLaunchKernelGGL(k_inverse_cols<VMC_PREC_MIXED>, dim3(c->nw), dim3(NT), c->lds, c->stream, c->dW, c->dS, c->dp,
+                       (double* const*)c->d_smB, 0, c->maxn, tol, c->d_nonconv);
+  HIPCHK(c, hipGetLastError());
+  int bad[256];
+  for (int w0 = 0; w0 < c->nw; w0 += 256) {
+    const int cnt = std::min(256, c->nw - w0);
+    HIPCHK(c, hipMemcpyAsync(bad, flags + w0, sizeof(int) * cnt, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < cnt; ++k) {
+      if (bad[k] < 0) { c->err = "walker " + std::to_string(w0 + k) + ": pending move or error"; return VMC_ESTATE; }
+      if (bad[k] > 0) {
+        c->err = "walker " + std::to_string(w0 + k) + ": " + std::to_string(bad[k]) +
+                 " inverse columns missed the tolerance";
+        return VMC_ENOCONV;
+      }
+    }
+  }
+  const vmc_status st = walker_errors(c);
+  c->sm_current = (st == VMC_OK);
+  return st;
+}
+
 vmc_status vmc_sm_run_steps(void* ctx, int32_t steps, vmc_step_record* dev_log, int64_t log_cap) {
   Ctx* c = (Ctx*)ctx;
   if (!c || steps < 0) return VMC_EINVAL;
   if (!c->d_smB) { c->err = "vmc_sm_run_steps before vmc_sm_prepare"; return VMC_ESTATE; }
+  if (c->sm_static && !sm_static_owned(c)) {
+    c->err = "the static inverses now belong to another context (vmc_sm_prepare_static)";
+    return VMC_ESTATE;
+  }
   if (!c->sm_current) {
     c->err = "the stored inverses are stale: the walkers have changed since vmc_sm_prepare";
     return VMC_ESTATE;
@@ -1355,7 +1477,9 @@ vmc_status vmc_sm_get_inverse(void* ctx, int32_t walker, double* host_out) {
   if (!c || !host_out || walker < 0 || walker >= c->nw) return VMC_EINVAL;
   if (!c->d_smB) { c->err = "no stored inverse (call vmc_sm_prepare)"; return VMC_ESTATE; }
   const int n = c->hw[walker].n;
-  HIPCHK(c, hipMemcpy2DAsync(host_out, (size_t)n * 8, c->sm_bufs[walker], sm_ld(n) * 8, (size_t)n * 8, n,
+  const void* src = c->sm_static ? sm_static_inverse(c, walker) : (const void*)c->sm_bufs[walker];
+  if (!src) { c->err = "the static inverses now belong to another context (vmc_sm_prepare_static)"; return VMC_ESTATE; }
+  HIPCHK(c, hipMemcpy2DAsync(host_out, (size_t)n * 8, src, sm_ld(n) * 8, (size_t)n * 8, n,
                              hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return VMC_OK;
@@ -1617,8 +1741,9 @@ vmc_status vmc_destroy(void* ctx) {
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (void* b : c->sm_bufs) (void)hipFree(b);
-  if (c->d_smB) (void)hipFree(c->d_smB);
-  if (c->d_nonconv) (void)hipFree(c->d_nonconv);
+  if (c->smB_own) (void)hipFree(c->smB_own);
+  if (c->nonconv_own) (void)hipFree(c->nonconv_own);
+  sm_static_release(c);
   delete c;
   return VMC_OK;
 }

@@ -53,7 +53,7 @@ EXPORTED = [
     "vmc_accept", "vmc_run_steps", "vmc_run_sweeps", "vmc_sync", "vmc_get_dims",
     "vmc_get_state", "vmc_get_stats", "vmc_last_error", "vmc_destroy", "vmc_phase_bench",
     "vmc_run_steps_graph", "vmc_autotune", "vmc_kinetic_energy", "vmc_run_steps_energy",
-    "vmc_sm_prepare", "vmc_sm_run_steps", "vmc_sm_get_inverse",
+    "vmc_sm_prepare", "vmc_sm_prepare_static", "vmc_sm_run_steps", "vmc_sm_get_inverse",
 ]
 PHASE_BENCH = {"spmv": 0, "lsolve": 1, "usolve": 2, "updates": 3, "resid64": 4, "ilutp": 5}
 
@@ -198,6 +198,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.vmc_kinetic_energy.argtypes = [P, P, i32, i32, i32, P, P]
     lib.vmc_run_steps_energy.argtypes = [P, i32, P, ctypes.c_int64, P, i32]
     lib.vmc_sm_prepare.argtypes = [P, ctypes.c_double]
+    lib.vmc_sm_prepare_static.argtypes = [P, ctypes.c_double]
     lib.vmc_sm_run_steps.argtypes = [P, i32, P, ctypes.c_int64]
     lib.vmc_sm_get_inverse.argtypes = [P, i32, P]
     for name in EXPORTED:
@@ -451,6 +452,11 @@ class Context:
     def sm_prepare(self, tol: float = 1e-13):
         """Explicit inverses for the standard algorithm (see vmc_sm_prepare)."""
         self._check(lib().vmc_sm_prepare(self.h, float(tol)))
+
+    def sm_prepare_static(self, tol: float = 1e-13):
+        """vmc_sm_prepare into the library's static device scratch (no device
+        allocation; see vmc_sm_prepare_static)."""
+        self._check(lib().vmc_sm_prepare_static(self.h, float(tol)))
 
     def sm_run_steps(self, steps: int, log: bool = False):
         """Steps by the standard algorithm; with log=True returns the step log
