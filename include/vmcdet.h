@@ -87,7 +87,9 @@ typedef struct vmc_params {
   double n_thresh;          /* reorder when the effective stability N exceeds this */
   double iter_factor;       /* reorder when iterations >= factor * running average */
   int32_t iter_min_solves;  /* solves before the iteration average is used */
-  double inner_rtol;        /* mixed: inner FP32 solve tolerance */
+  double inner_rtol;        /* mixed: tolerance of the first FP32 solve; a correction
+                               solve stops at max(inner_rtol, half the reduction the
+                               refinement target still needs) */
   double refine_tol;        /* mixed: converged when ||e_i - A z|| <= tol; refines on to
                                tol * min(1, |ratio|) within refine_maxit passes */
   int32_t refine_maxit;     /* mixed: maximum refinement passes */

@@ -675,7 +675,7 @@ vmc_status vmc_default_params(vmc_params* p) {
   p->iter_factor = 4.0;
   p->iter_min_solves = 10;
   p->inner_rtol = 1e-6;
-  p->refine_tol = 1e-11;
+  p->refine_tol = 1e-10;
   p->refine_maxit = 4;
   p->step = 0.25;
   p->row_cap = 0;

@@ -95,7 +95,7 @@ class Params:
     m_max: int = 32               # stored rank-one updates before a refactor
     mixed: bool = False           # FP32 Krylov / factors, FP64 refinement
     inner_rtol: float = 1e-6      # inner FP32 solve tolerance (mixed)
-    refine_tol: float = 1e-11     # refinement stop: ||r|| <= tol * min(1,|ratio|)
+    refine_tol: float = 1e-10     # refinement stop: ||r|| <= tol * min(1,|ratio|)
     refine_maxit: int = 4
     sweeps: int = 1
     ilu_work_cap: int = 0         # ILUTP work-row capacity (0: the library default)
