@@ -417,7 +417,7 @@ VMC_PHASE void wg_spmv(const Walker& W, const KT* aval, const KT* xs, KT* w) {
 }
 
 // r = e_unit - A z in FP64; returns ||r||_2.  z is staged in LDS when the
-// solve region can hold it, otherwise gathered from global memory.
+// stage_bytes at S.A can hold it, otherwise gathered from global memory.
 VMC_PHASE double wg_resid64(const Walker& W, const double* z, int unit, double* rv, Smem& S,
                                     size_t stage_bytes) {
   const int n = W.n;

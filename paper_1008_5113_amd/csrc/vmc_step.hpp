@@ -129,7 +129,9 @@ VMC_PHASE StepSolve wg_solve(const Walker& W, int m, const DevParams& P, Smem& S
     while (true) {
       PhaseClock pc;
       pc.start();
-      const size_t stage = align_up((size_t)W.n, 4) * 4 + align_up((size_t)DTILE * 4, 16);
+      // between the solves nothing in region A is live (the new row has been
+      // handed over in global memory), so all of it may stage z
+      const size_t stage = (size_t)((char*)S.red - S.A);
       const double rn = wg_resid64(W, W.zvec, i, W.rvec, S, stage);
       o.ratio = wg_ratio(W, ulen, W.zvec, S, base);
       pc.stop(S, PH_RESID);

@@ -433,7 +433,7 @@ __global__ void __launch_bounds__(NT, 4) k_phase(const Walker* __restrict__ walk
       case 2: wg_usolve<KT>(W, Fac<KT>::usval(W), Fac<KT>::dinv(W), xs, D, st); break;
       case 3: wg_updates<KT>(W, m, P.m_max, xs, S); break;
       case 4: {
-        const size_t stage = align_up((size_t)n, 4) * 4 + align_up((size_t)DTILE * 4, 16);
+        const size_t stage = (size_t)((char*)S.red - S.A);
         (void)wg_resid64(W, W.zvec, it % n, W.rvec, S, stage);
         for (int e = threadIdx.x; e < DTILE; e += NT) D[e] = (KT)0;
         break;
