@@ -377,8 +377,8 @@ vmc_status vmc_sm_prepare(void* ctx, double tol);
    hipMalloc, hipFree or other allocating routine (an error message may
    allocate host memory).  The inverses, their pointer table and the
    not-converged flags must fit 64 MiB: sum over walkers of
-   ceil8(n) * n * 8 bytes, each rounded up to 256, plus 256-byte-rounded
-   8 * walkers and 4 * walkers; larger requests return VMC_EINVAL and leave
+   n2 * n * 8 bytes (n2 = n rounded up to even), each rounded up to 256,
+   plus 256-byte-rounded 8 * walkers and 4 * walkers; larger requests return VMC_EINVAL and leave
    the context as it was.  One array per GPU: the last context to call this
    on a GPU owns it, and the contexts that held it before get VMC_ESTATE from
    vmc_sm_run_steps and vmc_sm_get_inverse until they prepare again.  Calls
