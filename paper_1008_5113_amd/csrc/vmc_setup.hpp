@@ -37,7 +37,44 @@ VMC_PHASE int wg_build_all_rows(const Walker& W, Smem& S) {
 // pivots; the identity after creation).  Squared minimum-image distances; ties
 // to the first position.  Writes rowperm/rpos and colsite/cpos (reorder order)
 // and reo_row/reo_col.
+// Two lexicographic minima (smaller value, then smaller index: the rule of
+// wg_argmin) reduced over the workgroup together, with one barrier.  buf
+// holds 2 * NWAVE doubles and 2 * NWAVE ints; a caller that reduces again
+// before a barrier of its own alternates between two such buffers.
+VMC_PHASE void wg_argmin2(double& v1, int& i1, double& v2, int& i2, double* buf) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double a = __shfl_xor(v1, o, 64);
+    const int ai = __shfl_xor(i1, o, 64);
+    if (a < v1 || (a == v1 && ai < i1)) { v1 = a; i1 = ai; }
+    const double b = __shfl_xor(v2, o, 64);
+    const int bi = __shfl_xor(i2, o, 64);
+    if (b < v2 || (b == v2 && bi < i2)) { v2 = b; i2 = bi; }
+  }
+  int* ib = (int*)(buf + 2 * NWAVE);
+  if (lane_id() == 0) {
+    buf[wave_id()] = v1;
+    buf[NWAVE + wave_id()] = v2;
+    ib[wave_id()] = i1;
+    ib[NWAVE + wave_id()] = i2;
+  }
+  __syncthreads();
+  v1 = buf[0];
+  i1 = ib[0];
+  v2 = buf[NWAVE];
+  i2 = ib[NWAVE];
+  for (int w = 1; w < NWAVE; ++w) {
+    const double a = buf[w];
+    const int ai = ib[w];
+    if (a < v1 || (a == v1 && ai < i1)) { v1 = a; i1 = ai; }
+    const double b = buf[NWAVE + w];
+    const int bi = ib[NWAVE + w];
+    if (b < v2 || (b == v2 && bi < i2)) { v2 = b; i2 = bi; }
+  }
+}
+
 VMC_PHASE void wg_reorder(const Walker& W, Smem& S) {
+  constexpr int RU = 2;
   const int n = W.n;
   short* rp = (short*)S.A;
   short* cp = rp + align_up((size_t)n, 8);
@@ -47,35 +84,54 @@ VMC_PHASE void wg_reorder(const Walker& W, Smem& S) {
   }
   __syncthreads();
   for (int i = 0; i < n - 1; ++i) {
+    // Both searches of position i scan positions i..n-1 in one pass: the
+    // closest orbital to the particle at i and, for the case that this
+    // orbital already is at i, the closest particle to the orbital at i
+    // (nothing moves between the two searches, so the second one's answer is
+    // the one the sequential order would find).
     const int pi = rp[i];
     const double rx = W.pos[3 * pi], ry = W.pos[3 * pi + 1], rz = W.pos[3 * pi + 2];
-    double best = INFINITY;
-    int bj = 0x7fffffff;
-    for (int j = i + vmc_tid(); j < n; j += NT) {
-      double dx;
-      double d2 = dist2_xyz(rx, ry, rz, W.sites + 3 * (size_t)cp[j], W.box, &dx);
-      if (d2 < best) { best = d2; bj = j; }
-    }
-    wg_argmin(best, bj, S.red);
-    if (bj != i) {
-      __syncthreads();
-      if (vmc_tid() == 0) { short t = cp[i]; cp[i] = cp[bj]; cp[bj] = t; }
-      __syncthreads();
-      continue;
-    }
     const double* Zi = W.sites + 3 * (size_t)cp[i];
-    best = INFINITY;
-    int bk = 0x7fffffff;
-    for (int k = i + vmc_tid(); k < n; k += NT) {
-      const int pk = rp[k];
-      double dx;
-      double d2 = dist2_xyz(W.pos[3 * pk], W.pos[3 * pk + 1], W.pos[3 * pk + 2], Zi, W.box, &dx);
-      if (d2 < best) { best = d2; bk = k; }
+    double bo = INFINITY, bq = INFINITY;
+    int jo = 0x7fffffff, kq = 0x7fffffff;
+    // RU positions per thread at a time: their coordinates are gathered
+    // before any is compared, so the loads overlap; the comparisons then run
+    // in ascending position, as a plain strided loop would
+    for (int t0 = i + vmc_tid(); t0 < n; t0 += RU * NT) {
+      double cs[RU][3], cr[RU][3];
+#pragma unroll
+      for (int q = 0; q < RU; ++q) {
+        const int t = t0 + q * NT;
+        const int tc = t < n ? t : i;
+        const double* Z = W.sites + 3 * (size_t)cp[tc];
+        const double* R = W.pos + 3 * (size_t)rp[tc];
+        cs[q][0] = Z[0];
+        cs[q][1] = Z[1];
+        cs[q][2] = Z[2];
+        cr[q][0] = R[0];
+        cr[q][1] = R[1];
+        cr[q][2] = R[2];
+      }
+#pragma unroll
+      for (int q = 0; q < RU; ++q) {
+        const int t = t0 + q * NT;
+        double dx;
+        const double d1 = dist2_xyz(rx, ry, rz, cs[q], W.box, &dx);
+        if (t < n && d1 < bo) { bo = d1; jo = t; }
+        const double d2 = dist2_xyz(cr[q][0], cr[q][1], cr[q][2], Zi, W.box, &dx);
+        if (t < n && d2 < bq) { bq = d2; kq = t; }
+      }
     }
-    wg_argmin(best, bk, S.red);
-    __syncthreads();
-    if (bk != i && vmc_tid() == 0) { short t = rp[i]; rp[i] = rp[bk]; rp[bk] = t; }
-    __syncthreads();
+    // every thread's scan is done once the reduction's barrier is passed, so
+    // thread 0 may swap right away; the decision is the same in every thread
+    wg_argmin2(bo, jo, bq, kq, S.red + (i & 1) * 4 * NWAVE);
+    if (jo != i) {
+      if (vmc_tid() == 0) { short t = cp[i]; cp[i] = cp[jo]; cp[jo] = t; }
+      __syncthreads();
+    } else if (kq != i) {
+      if (vmc_tid() == 0) { short t = rp[i]; rp[i] = rp[kq]; rp[kq] = t; }
+      __syncthreads();
+    }
   }
   for (int k = vmc_tid(); k < n; k += NT) {
     const int p = rp[k], s = cp[k];
