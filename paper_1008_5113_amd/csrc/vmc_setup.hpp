@@ -73,63 +73,191 @@ VMC_PHASE void wg_argmin2(double& v1, int& i1, double& v2, int& i2, double* buf)
   }
 }
 
-VMC_PHASE void wg_reorder(const Walker& W, Smem& S) {
+VMC_PHASE void wg_exclusive_scan(const int* len, int* ptr, int n, Smem& S);
+
+// Lattice cell of a point in [0, L) (a point at L rounds into the last cell).
+__device__ inline int lattice_cell(const Walker& W, double x, double y, double z) {
+  const int ix = min(max((int)floor(x / W.a), 0), W.lat[0] - 1);
+  const int iy = min(max((int)floor(y / W.a), 0), W.lat[1] - 1);
+  const int iz = min(max((int)floor(z / W.a), 0), W.lat[2] - 1);
+  return ix + W.lat[0] * (iy + W.lat[1] * iz);
+}
+
+// Lexicographic (distance, position) minimum update.
+__device__ inline void lex_min(double d, int p, double& bd, int& bp) {
+  if (d < bd || (d == bd && p < bp)) { bd = d; bp = p; }
+}
+
+// scratch (global, scratch_bytes long, free during the reorder) holds the
+// particles' cell lists when it is large enough, and the LDS region then also
+// holds both inverse permutations: each step first searches the lattice cells
+// within one lattice spacing of the particle (orbitals) and of the orbital
+// (particles), and only when a search finds nothing closer than that radius
+// falls back to the scan of every free position.  The minimum over (distance,
+// position) pairs is the same either way: every free site or particle within
+// the radius lies in the cells searched, and any other is farther.  The cell
+// search keeps a step's cost flat in n (Section 3.1 notes that an O(n)
+// reorder is possible for sparse Slater matrices); while few positions are
+// free, the scan is cheaper and is used instead.
+VMC_PHASE void wg_reorder(const Walker& W, Smem& S, void* scratch, size_t scratch_bytes) {
   constexpr int RU = 2;
   const int n = W.n;
+  const size_t an = align_up((size_t)n, 8);
   short* rp = (short*)S.A;
-  short* cp = rp + align_up((size_t)n, 8);
+  short* cp = rp + an;
+  short* rposl = cp + an;
+  short* cposl = rposl + an;
+  const int L0 = W.lat[0], L1 = W.lat[1], L2 = W.lat[2], nb = W.nb;
+  const int ncell = L0 * L1 * L2;
+  const bool cells = (size_t)((char*)S.red - S.A) >= 4 * an * sizeof(short) && ncell * nb == n &&
+                     scratch != nullptr && scratch_bytes >= ((size_t)2 * ncell + 1 + n) * sizeof(int);
+  int* ccount = (int*)scratch;
+  int* cstart = ccount + ncell;
+  int* citem = cstart + ncell + 1;
   for (int k = vmc_tid(); k < n; k += NT) {
     rp[k] = (short)W.reo_row[k];
     cp[k] = (short)W.reo_col[k];
   }
   __syncthreads();
+  if (cells) {
+    for (int k = vmc_tid(); k < n; k += NT) {
+      rposl[rp[k]] = (short)k;
+      cposl[cp[k]] = (short)k;
+    }
+    for (int c = vmc_tid(); c < ncell; c += NT) ccount[c] = 0;
+    __threadfence_block();
+    __syncthreads();
+    for (int p = vmc_tid(); p < n; p += NT)
+      atomicAdd(&ccount[lattice_cell(W, W.pos[3 * p], W.pos[3 * p + 1], W.pos[3 * p + 2])], 1);
+    __threadfence_block();
+    __syncthreads();
+    wg_exclusive_scan(ccount, cstart, ncell, S);
+    for (int c = vmc_tid(); c < ncell; c += NT) ccount[c] = 0;
+    __threadfence_block();
+    __syncthreads();
+    for (int p = vmc_tid(); p < n; p += NT) {
+      const int c = lattice_cell(W, W.pos[3 * p], W.pos[3 * p + 1], W.pos[3 * p + 2]);
+      citem[cstart[c] + atomicAdd(&ccount[c], 1)] = p;
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  const double RL = W.a;
+  // below RL^2 by far more than the rounding of a squared distance
+  const double cert = 0.999 * RL * RL;
+  int rb = 0;
   for (int i = 0; i < n - 1; ++i) {
-    // Both searches of position i scan positions i..n-1 in one pass: the
-    // closest orbital to the particle at i and, for the case that this
-    // orbital already is at i, the closest particle to the orbital at i
-    // (nothing moves between the two searches, so the second one's answer is
-    // the one the sequential order would find).
     const int pi = rp[i];
     const double rx = W.pos[3 * pi], ry = W.pos[3 * pi + 1], rz = W.pos[3 * pi + 2];
     const double* Zi = W.sites + 3 * (size_t)cp[i];
     double bo = INFINITY, bq = INFINITY;
     int jo = 0x7fffffff, kq = 0x7fffffff;
-    // RU positions per thread at a time: their coordinates are gathered
-    // before any is compared, so the loads overlap; the comparisons then run
-    // in ascending position, as a plain strided loop would
-    for (int t0 = i + vmc_tid(); t0 < n; t0 += RU * NT) {
-      double cs[RU][3], cr[RU][3];
-#pragma unroll
-      for (int q = 0; q < RU; ++q) {
-        const int t = t0 + q * NT;
-        const int tc = t < n ? t : i;
-        const double* Z = W.sites + 3 * (size_t)cp[tc];
-        const double* R = W.pos + 3 * (size_t)rp[tc];
-        cs[q][0] = Z[0];
-        cs[q][1] = Z[1];
-        cs[q][2] = Z[2];
-        cr[q][0] = R[0];
-        cr[q][1] = R[1];
-        cr[q][2] = R[2];
+    bool local = false;
+    // the scan costs one gather round per RU * NT free positions, the cell
+    // search about three (measured): cells only while many are free
+    if (cells && n - i > 6 * NT) {
+      // free orbitals in the cells around the particle (the row builder's
+      // enumeration, for radius RL)
+      int lox, cx, loy, cy, loz, cz;
+      axis_range(rx - W.bmax[0], RL + W.margin, W.a, L0, lox, cx);
+      axis_range(ry - W.bmax[1], RL + W.margin, W.a, L1, loy, cy);
+      axis_range(rz - W.bmax[2], RL + W.margin, W.a, L2, loz, cz);
+      const int tot = cx * cy * cz * nb;
+      for (int t = vmc_tid(); t < tot; t += NT) {
+        const int b = t % nb, cell = t / nb;
+        const int ix = wrap_index(lox + cell % cx, L0);
+        const int iy = wrap_index(loy + (cell / cx) % cy, L1);
+        const int iz = wrap_index(loz + cell / (cx * cy), L2);
+        const int site = b + nb * (ix + L0 * (iy + L1 * iz));
+        const int ps = cposl[site];
+        if (ps >= i) {
+          double dx;
+          lex_min(dist2_xyz(rx, ry, rz, W.sites + 3 * (size_t)site, W.box, &dx), ps, bo, jo);
+        }
       }
-#pragma unroll
-      for (int q = 0; q < RU; ++q) {
-        const int t = t0 + q * NT;
-        double dx;
-        const double d1 = dist2_xyz(rx, ry, rz, cs[q], W.box, &dx);
-        if (t < n && d1 < bo) { bo = d1; jo = t; }
-        const double d2 = dist2_xyz(cr[q][0], cr[q][1], cr[q][2], Zi, W.box, &dx);
-        if (t < n && d2 < bq) { bq = d2; kq = t; }
+      // free particles in the cells around the orbital at i
+      axis_range(Zi[0], RL, W.a, L0, lox, cx);
+      axis_range(Zi[1], RL, W.a, L1, loy, cy);
+      axis_range(Zi[2], RL, W.a, L2, loz, cz);
+      const int ptot = cx * cy * cz;
+      for (int t = vmc_tid(); t < ptot; t += NT) {
+        const int ix = wrap_index(lox + t % cx, L0);
+        const int iy = wrap_index(loy + (t / cx) % cy, L1);
+        const int iz = wrap_index(loz + t / (cx * cy), L2);
+        const int c = ix + L0 * (iy + L1 * iz);
+        for (int e = cstart[c]; e < cstart[c + 1]; ++e) {
+          const int p = citem[e];
+          const int pp = rposl[p];
+          if (pp >= i) {
+            double dx;
+            lex_min(dist2_xyz(W.pos[3 * p], W.pos[3 * p + 1], W.pos[3 * p + 2], Zi, W.box, &dx), pp, bq, kq);
+          }
+        }
       }
+      wg_argmin2(bo, jo, bq, kq, S.red + (rb++ & 1) * 4 * NWAVE);
+      local = bo < cert && (jo != i || bq < cert);
     }
-    // every thread's scan is done once the reduction's barrier is passed, so
-    // thread 0 may swap right away; the decision is the same in every thread
-    wg_argmin2(bo, jo, bq, kq, S.red + (i & 1) * 4 * NWAVE);
+    if (!local) {
+      // Both searches of position i scan positions i..n-1 in one pass: the
+      // closest orbital to the particle at i and, for the case that this
+      // orbital already is at i, the closest particle to the orbital at i
+      // (nothing moves between the two searches, so the second one's answer
+      // is the one the sequential order would find).
+      bo = bq = INFINITY;
+      jo = kq = 0x7fffffff;
+      // RU positions per thread at a time: their coordinates are gathered
+      // before any is compared, so the loads overlap; the comparisons then
+      // run in ascending position, as a plain strided loop would
+      for (int t0 = i + vmc_tid(); t0 < n; t0 += RU * NT) {
+        double cs[RU][3], cr[RU][3];
+#pragma unroll
+        for (int q = 0; q < RU; ++q) {
+          const int t = t0 + q * NT;
+          const int tc = t < n ? t : i;
+          const double* Z = W.sites + 3 * (size_t)cp[tc];
+          const double* R = W.pos + 3 * (size_t)rp[tc];
+          cs[q][0] = Z[0];
+          cs[q][1] = Z[1];
+          cs[q][2] = Z[2];
+          cr[q][0] = R[0];
+          cr[q][1] = R[1];
+          cr[q][2] = R[2];
+        }
+#pragma unroll
+        for (int q = 0; q < RU; ++q) {
+          const int t = t0 + q * NT;
+          double dx;
+          const double d1 = dist2_xyz(rx, ry, rz, cs[q], W.box, &dx);
+          if (t < n && d1 < bo) { bo = d1; jo = t; }
+          const double d2 = dist2_xyz(cr[q][0], cr[q][1], cr[q][2], Zi, W.box, &dx);
+          if (t < n && d2 < bq) { bq = d2; kq = t; }
+        }
+      }
+      wg_argmin2(bo, jo, bq, kq, S.red + (rb++ & 1) * 4 * NWAVE);
+    }
+    // every thread's search is done once the reduction's barrier is passed,
+    // so thread 0 may swap right away; the decision is the same everywhere
     if (jo != i) {
-      if (vmc_tid() == 0) { short t = cp[i]; cp[i] = cp[jo]; cp[jo] = t; }
+      if (vmc_tid() == 0) {
+        const short a = cp[i], b = cp[jo];
+        cp[i] = b;
+        cp[jo] = a;
+        if (cells) {
+          cposl[b] = (short)i;
+          cposl[a] = (short)jo;
+        }
+      }
       __syncthreads();
     } else if (kq != i) {
-      if (vmc_tid() == 0) { short t = rp[i]; rp[i] = rp[kq]; rp[kq] = t; }
+      if (vmc_tid() == 0) {
+        const short a = rp[i], b = rp[kq];
+        rp[i] = b;
+        rp[kq] = a;
+        if (cells) {
+          rposl[b] = (short)i;
+          rposl[a] = (short)kq;
+        }
+      }
       __syncthreads();
     }
   }

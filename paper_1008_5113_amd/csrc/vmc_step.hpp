@@ -167,7 +167,8 @@ template <int PREC>
 VMC_PHASE int wg_reorder_refactor(const Walker& W, const DevParams& P, Smem& S) {
   PhaseClock pc;
   pc.start();
-  wg_reorder(W, S);
+  // the Krylov basis is free between solves: the reorder's cell lists
+  wg_reorder(W, S, (void*)W.V, (size_t)(P.maxit + 1) * W.n * (PREC == VMC_PREC_FP64 ? 8 : 4));
   int st = wg_build_all_rows(W, S);
   pc.stop(S, PH_REORDER);
   if (st != WST_OK) return st;

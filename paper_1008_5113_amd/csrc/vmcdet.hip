@@ -48,7 +48,8 @@ __global__ void __launch_bounds__(NT) k_setup(const Walker* __restrict__ walkers
   // a rebuild or refactor starts the walker afresh: earlier errors are
   // re-detected if they persist
   if (threadIdx.x == 0) states[w].status = WST_OK;
-  if (mode & MODE_REORDER) wg_reorder(W, S);
+  if (mode & MODE_REORDER)
+    wg_reorder(W, S, (void*)W.V, (size_t)(P.maxit + 1) * W.n * (PREC == VMC_PREC_FP64 ? 8 : 4));
   if (mode & (MODE_BUILD | MODE_REORDER)) st |= wg_build_all_rows(W, S);
   PhaseClock pc;
   pc.start();
