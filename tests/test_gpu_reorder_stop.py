@@ -65,6 +65,34 @@ def test_reorder_chained_bitexact(vm):
     ctx.close()
 
 
+@pytest.mark.parametrize("which", ["p_like_n4000", "jittered_n8192"])
+def test_reorder_cell_search_bitexact(vm, which):
+    """At n = 4000 and 8192 the first steps of a reorder search lattice cells
+    around the particle and the orbital instead of scanning every free
+    position; the permutation must still be the oracle's exactly, from the
+    identity and chained after a stretch of steps (jittered sites and
+    lognormal widths in the second case)."""
+    _say(f"case: cell-search reorder {which}")
+    if which == "p_like_n4000":
+        inst = wl.mixed_n4000(n_walkers=1)
+    else:
+        inst = wl.stress_n8192(n_walkers=1)
+    s = inst.systems[0]
+    ctx = vm.Context.from_instance(inst)
+    ctx.ilutp(reorder=True)
+    st = ctx.state(0)
+    row, col = geometric_reorder(inst.walkers[0].pos0, s)
+    assert np.array_equal(st["reorder_row"], row) and np.array_equal(st["reorder_col"], col)
+    ctx.run_steps(400)
+    ctx.sync()
+    before = ctx.state(0)
+    ctx.ilutp(reorder=True)
+    st = ctx.state(0)
+    row, col = geometric_reorder(before["pos"], s, before["reorder_row"], before["reorder_col"])
+    assert np.array_equal(st["reorder_row"], row) and np.array_equal(st["reorder_col"], col)
+    ctx.close()
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_plain_stop_against_ratio_relative_stop(vm, precision):
     """The same chain with the default stop (iterate on to tol * min(1,
